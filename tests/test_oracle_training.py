@@ -1,0 +1,217 @@
+"""Pins of the oracle's MLP, losses, gradients and Adam (Sec. 3.3, Sec. 3.4)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import hashgrid, mlp, training
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _hand():
+    with open(os.path.join(GOLD, "mlp_two_layer_hand.json")) as f:
+        return json.load(f)
+
+
+def test_two_layer_hand_example_forward_and_backward():
+    g = _hand()
+    W = [np.array(g["W1"]), np.array(g["W2"])]
+    enc = np.array([g["enc"]])
+    z, pre, inputs = mlp.forward(enc, W)
+    assert z[0, 0] == g["z"]
+    assert abs(mlp.sigmoid(z)[0, 0] - g["v"]) < 1e-17
+    loss, dz = training.bce_loss(z, np.array([[g["label"]]]))
+    assert abs(loss - g["loss"]) < 1e-14
+    assert abs(dz[0, 0] - g["dz"]) < 1e-16
+    dW, d_enc = mlp.backward(W, pre, inputs, dz)
+    assert np.allclose(dW[0], g["dW1"], rtol=0, atol=1e-15)
+    assert np.allclose(dW[1], g["dW2"], rtol=0, atol=1e-15)
+    assert np.allclose(d_enc[0], g["d_enc"], rtol=0, atol=1e-15)
+
+
+def test_sigmoid_special_values():
+    z = np.array([0.0, 1000.0, -1000.0, 3.0, -3.0])
+    s = mlp.sigmoid(z)
+    assert s[0] == 0.5 and s[1] == 1.0 and s[2] == 0.0
+    assert abs(s[3] + s[4] - 1.0) <= 2.3e-16
+    assert np.all(np.isfinite(s))
+
+
+def _torch_net(weights, kind, slope):
+    layers = []
+    for k, W in enumerate(weights):
+        lin = torch.nn.Linear(W.shape[1], W.shape[0], bias=False).double()
+        with torch.no_grad():
+            lin.weight.copy_(torch.from_numpy(np.asarray(W, np.float64)))
+        layers.append(lin)
+        if k < len(weights) - 1:
+            layers.append(torch.nn.ReLU() if kind == "relu" else torch.nn.LeakyReLU(slope))
+    return torch.nn.Sequential(*layers)
+
+
+@pytest.mark.parametrize("kind", ["relu", "leaky"])
+def test_forward_backward_match_torch_autograd(kind):
+    rng = np.random.default_rng(0)
+    shapes = [(64, 32), (64, 64), (64, 64), (32, 64)]
+    weights = [rng.normal(scale=1 / math.sqrt(i), size=(o, i)) for o, i in shapes]
+    enc = rng.normal(size=(300, 32))
+    y = (rng.uniform(size=(300, 32)) > 0.4).astype(np.float64)
+    z, pre, inputs = mlp.forward(enc, weights, kind)
+    loss, dz = training.bce_loss(z, y)
+    dW, d_enc = mlp.backward(weights, pre, inputs, dz, kind)
+
+    net = _torch_net(weights, kind, 0.01)
+    x = torch.from_numpy(enc).requires_grad_(True)
+    zt = net(x)
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(zt, torch.from_numpy(y))
+    lt.backward()
+    assert np.max(np.abs(zt.detach().numpy() - z)) < 1e-12
+    assert abs(lt.item() - loss) < 1e-13
+    lin = [m for m in net if isinstance(m, torch.nn.Linear)]
+    for k in range(len(weights)):
+        ref = lin[k].weight.grad.numpy()
+        assert np.max(np.abs(ref - dW[k])) <= 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(x.grad.numpy() - d_enc)) < 1e-13
+
+
+def test_l2_loss_matches_torch():
+    rng = np.random.default_rng(1)
+    z = rng.normal(size=(50, 8))
+    y = (rng.uniform(size=(50, 8)) > 0.5).astype(np.float64)
+    loss, dz = training.l2_loss(z, y)
+    zt = torch.from_numpy(z).requires_grad_(True)
+    lt = torch.nn.functional.mse_loss(torch.sigmoid(zt), torch.from_numpy(y))
+    lt.backward()
+    assert abs(lt.item() - loss) < 1e-14
+    assert np.max(np.abs(zt.grad.numpy() - dz)) < 1e-16
+
+
+def test_bce_closed_forms():
+    # z = 0: loss log 2 whatever the label, gradient (1/2 - y)/n.
+    z = np.zeros((4, 2))
+    y = np.array([[0, 1], [1, 0], [1, 1], [0, 0]], np.float64)
+    loss, dz = training.bce_loss(z, y)
+    assert abs(loss - math.log(2.0)) < 1e-15
+    assert np.allclose(dz, (0.5 - y) / 8, atol=0)
+    # large |z| stays finite
+    loss, dz = training.bce_loss(np.array([[800.0, -800.0]]), np.array([[0.0, 1.0]]))
+    assert abs(loss - 800.0) < 1e-9 and np.all(np.isfinite(dz))
+
+
+def test_full_gradient_matches_torch_autograd_through_the_encoding():
+    """Table and weight gradients of the whole path against torch FP64 autograd.
+
+    torch gathers the 8 corners (indices and trilinear weights from the pinned
+    hash-grid oracle) and differentiates the gather, so the scatter of
+    `training.table_gradient` is checked by an independent route.
+    """
+    rng = np.random.default_rng(3)
+    L, T, F = 8, 1 << 10, 2
+    base, growth = 4, 1.5
+    table = rng.uniform(-0.5, 0.5, size=(L, T, F)).astype(np.float32)
+    shapes = [(32, 16), (32, 32), (8, 32)]
+    weights = [rng.normal(scale=0.5, size=s).astype(np.float32) for s in shapes]
+    pos = rng.uniform(0, 1, size=(256, 3)).astype(np.float32)
+    y = (rng.uniform(size=(256, 8)) > 0.5).astype(np.float64)
+    out = training.train_gradients(pos, table, weights, base, growth, labels=y, loss="bce")
+
+    tt = torch.from_numpy(table.astype(np.float64)).requires_grad_(True)
+    ws = [torch.from_numpy(w.astype(np.float64)).requires_grad_(True) for w in weights]
+    res = hashgrid.level_resolutions(base, growth, L)
+    feats = []
+    for l in range(L):
+        idx, w = hashgrid.corners(pos, res[l], T)
+        vals = tt[l][torch.from_numpy(idx)]                       # [n,8,F]
+        feats.append((torch.from_numpy(w)[:, :, None] * vals).sum(1))
+    h = torch.cat(feats, 1)
+    for k, W in enumerate(ws):
+        h = h @ W.T
+        if k < len(ws) - 1:
+            h = torch.relu(h)
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(h, torch.from_numpy(y))
+    lt.backward()
+    assert abs(lt.item() - out["loss"]) < 1e-13
+    assert np.max(np.abs(tt.grad.numpy() - out["g_table"])) < 1e-15
+    for k in range(len(ws)):
+        assert np.max(np.abs(ws[k].grad.numpy() - out["g_w"][k])) < 1e-14
+
+
+def test_central_finite_differences():
+    """Central differences (h = 1e-3, FP64) on weights, touched table entries and random directions.
+
+    The trilinear encoding is linear in the table, so those differences are
+    exact up to rounding; for weights, perturbations that flip a ReLU mask are
+    skipped (detected by comparing masks).
+    """
+    rng = np.random.default_rng(11)
+    L, T, F = 4, 1 << 8, 2
+    base, growth = 4, 1.5
+    table = rng.uniform(-0.5, 0.5, size=(L, T, F))
+    shapes = [(16, 8), (16, 16), (4, 16)]
+    weights = [rng.normal(scale=0.6, size=s) for s in shapes]
+    pos = rng.uniform(0, 1, size=(64, 3)).astype(np.float32)
+    y = (rng.uniform(size=(64, 4)) > 0.5).astype(np.float64)
+    out = training.train_gradients(pos, table, weights, base, growth, labels=y)
+
+    def loss_and_masks(tab, ws):
+        enc = hashgrid.encode(pos, tab, base, growth)
+        z, pre, _ = mlp.forward(enc, ws)
+        return training.bce_loss(z, y)[0], [p > 0 for p in pre]
+
+    _, masks0 = loss_and_masks(table, weights)
+    h = 1e-3
+    checked = 0
+    for k, W in enumerate(weights):
+        for _ in range(12):
+            i, j = rng.integers(0, W.shape[0]), rng.integers(0, W.shape[1])
+            wp = [w.copy() for w in weights]
+            wm = [w.copy() for w in weights]
+            wp[k][i, j] += h
+            wm[k][i, j] -= h
+            lp, mp = loss_and_masks(table, wp)
+            lm, mm = loss_and_masks(table, wm)
+            if any((a != b).any() for a, b in zip(mp, masks0)) or any((a != b).any() for a, b in zip(mm, masks0)):
+                continue
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - out["g_w"][k][i, j]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-9
+            checked += 1
+    touched = np.argwhere(np.abs(out["g_table"]) > 0)
+    for l, t, f in touched[rng.choice(len(touched), 40, replace=False)]:
+        tp, tm = table.copy(), table.copy()
+        tp[l, t, f] += h
+        tm[l, t, f] -= h
+        lp, mp = loss_and_masks(tp, weights)
+        lm, mm = loss_and_masks(tm, weights)
+        if any((a != b).any() for a, b in zip(mp, masks0)) or any((a != b).any() for a, b in zip(mm, masks0)):
+            continue
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - out["g_table"][l, t, f]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-10
+        checked += 1
+    assert checked > 40
+
+
+def test_adam_matches_torch_optim_adam_ten_steps():
+    rng = np.random.default_rng(5)
+    p0 = rng.normal(size=1000)
+    grads = [rng.normal(size=1000) * (0.1 ** rng.integers(0, 4)) for _ in range(10)]
+    grads[3][::7] = 0.0
+    pt = torch.from_numpy(p0.copy()).requires_grad_(True)
+    opt = torch.optim.Adam([pt], lr=1e-2, betas=(0.9, 0.99), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(1000), np.zeros(1000)
+    for t, g in enumerate(grads, start=1):
+        pt.grad = torch.from_numpy(g.copy())
+        opt.step()
+        p, m, v = training.adam_step(p, g, m, v, t, 1e-2, 0.9, 0.99, 1e-8)
+        assert np.max(np.abs(pt.detach().numpy() - p)) <= 1e-12 * np.max(np.abs(p))
+
+
+def test_adam_first_step_closed_form():
+    # t = 1: m_hat = g, v_hat = g^2, so the step is lr * g / (|g| + eps).
+    g = np.array([1.0, -2.0, 1e-3, 0.0])
+    p, m, v = training.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.5, 0.9, 0.99, 1e-8)
+    assert np.allclose(p, -0.5 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.01 * g * g)
