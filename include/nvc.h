@@ -1,0 +1,209 @@
+/*
+ * nvc.h -- C ABI of the neural visibility cache hot path on MI355X (gfx950).
+ *
+ * The cache (Boksansky & Meister, "Neural Visibility Cache for Real-Time
+ * Light Sampling", JCGT 14(2), 2025) answers: given a 3D position, how
+ * visible is each light?  A multi-resolution hash-grid encoding feeds a small
+ * MLP with one sigmoid output per light (Sec. 3.1, Fig. "overview"; Sec. 3.3);
+ * a light is then picked by weighted reservoir sampling with weights equal to
+ * the unshadowed contribution times the clamped predicted visibility
+ * (Sec. 1, Sec. 3.1); the network is fitted online to shadow-ray labels with
+ * one Adam step per frame (Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (hipMalloc'd, coarse-grained) unless
+ *    marked "host".  The caller owns all memory; the library allocates
+ *    nothing and keeps no state between calls.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work on that stream: it never synchronises, so the results are
+ *    ready when the stream is.  Calls are safe to capture into a HIP graph
+ *    (no allocation, no memset, no host synchronisation inside).
+ *  - Arguments are validated on the host before anything is launched; a
+ *    negative nvc_status is returned and nothing is enqueued.  A failed
+ *    launch returns NVC_ERR_HIP.  There is no device-side error reporting.
+ *  - n == 0 (or batch == 0) is a valid no-op returning NVC_OK.
+ *  - NaN or Inf inputs are not checked; they propagate into the outputs.
+ *  - Layouts are row-major and dense (no strides).
+ */
+#ifndef NVC_H
+#define NVC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NVC_VERSION 1
+
+typedef enum nvc_status {
+    NVC_OK = 0,
+    NVC_ERR_NULL = -1,        /* a required pointer is NULL                        */
+    NVC_ERR_SHAPE = -2,       /* a size is negative, inconsistent or out of range  */
+    NVC_ERR_DTYPE = -3,       /* unknown dtype code                                */
+    NVC_ERR_UNSUPPORTED = -4, /* valid but not built: network shape, F, L*F, ...   */
+    NVC_ERR_HIP = -5,         /* a HIP launch failed                               */
+    NVC_ERR_WORKSPACE = -6    /* workspace missing or smaller than required        */
+} nvc_status;
+
+typedef enum nvc_dtype { NVC_F32 = 0, NVC_F16 = 1, NVC_BF16 = 2 } nvc_dtype;
+typedef enum nvc_act { NVC_ACT_RELU = 0, NVC_ACT_LEAKY = 1 } nvc_act;
+typedef enum nvc_loss { NVC_LOSS_BCE = 0, NVC_LOSS_L2 = 1 } nvc_loss;
+
+/* Multi-resolution hash grid (Sec. 3.3; Mueller et al. 2022 eq. 2-4), host struct.
+ * Level l has resolution N_l = floor(base_res * growth^l) (FP64 on the host);
+ * it is stored densely (vertex x + (N+1)y + (N+1)^2 z) when (N_l+1)^3 <= T,
+ * otherwise through the spatial hash (x*1 ^ y*2654435761 ^ z*805459861) mod T.
+ * Table layout: float32 [n_levels][T = 2^log2_T][n_feat], level-major.
+ * Supported: n_feat in {1, 2, 4}; 1 <= n_levels <= 32; n_levels*n_feat <= 64;
+ * 10 <= log2_T <= 24; 1 <= base_res; growth >= 1. */
+typedef struct nvc_grid {
+    int32_t n_levels;
+    int32_t n_feat;
+    int32_t log2_T;
+    int32_t base_res;
+    double growth;
+} nvc_grid;
+
+/* Visibility MLP (Sec. 3.3), host struct: n_in -> width (x n_hidden) -> n_out,
+ * no biases, hidden activation `act` (NVC_ACT_LEAKY uses leaky_slope), sigmoid
+ * output.  `dtype` is the precision of weights and activations fed to the
+ * matrix cores (NVC_F32 uses FP32 matrix cores); accumulation is FP32.
+ * n_in must equal n_levels * n_feat of the grid it is used with.
+ * Master weights: float32, the layers' row-major [out][in] matrices
+ * concatenated, input layer first (nvc_mlp_param_count floats). */
+typedef struct nvc_mlp {
+    int32_t n_in;
+    int32_t width;
+    int32_t n_hidden;
+    int32_t n_out;
+    int32_t act;
+    float leaky_slope;
+    int32_t dtype;
+} nvc_mlp;
+
+int nvc_version(void);
+
+/* Short English description of a status code (static storage). */
+const char* nvc_status_string(int status);
+
+/* Host only.  Level resolutions N_l and dense flags (1 dense, 0 hashed) of a
+ * grid, each written to host arrays of n_levels entries (either may be NULL). */
+int nvc_grid_levels(const nvc_grid* grid, int32_t* res, int32_t* dense);
+
+/* Host only.  Number of FP32 master weights of the network, or a negative status. */
+int64_t nvc_mlp_param_count(const nvc_mlp* mlp);
+
+/* Host only.  Bytes of the packed low-precision copy of the weights that
+ * nvc_infer and nvc_train_step read, or a negative status.  The packed copy
+ * holds, per layer, the matrix and its transpose cut into matrix-core
+ * operand fragments, in mlp->dtype. */
+int64_t nvc_mlp_packed_bytes(const nvc_mlp* mlp);
+
+/* Cast and reorder FP32 master weights `w` (nvc_mlp_param_count floats) into
+ * the packed buffer `packed` (nvc_mlp_packed_bytes bytes).  Call after every
+ * change of the master weights (e.g. after nvc_adam). */
+int nvc_pack_mlp(const nvc_mlp* mlp, const float* w, void* packed, void* stream);
+
+/* Hash-grid encoding (Sec. 3.1 Fig. "overview" step 1).
+ * table: float32 [L][T][F]; pos: float32 [n][3], unit cube (values are
+ * clamped to [0,1], NaN -> 0); enc: [n][L*F] in enc_dtype, feature j of level
+ * l at column l*F + j.  The cell of a position is decided in FP32:
+ * s = fl32(x * N_l), c = min(floor(s), N_l - 1); weights are trilinear in s - c. */
+int nvc_encode(const nvc_grid* grid, const float* table, const float* pos, int64_t n,
+               void* enc, int32_t enc_dtype, void* stream);
+
+/* Cache inference (Sec. 3.1 steps 1-2; Sec. 3.3): encoding followed by the
+ * MLP, fused in one kernel.  vis: [n][n_out] in vis_dtype, the raw sigmoid
+ * output in (0,1) (the clamp of Sec. 3.1 is applied by nvc_sample_wrs).
+ * packed: the output of nvc_pack_mlp for the same mlp.
+ * Built network shapes: n_in in {16, 32, 40}, width in {32, 64, 128},
+ * 1 <= n_hidden <= 4, 1 <= n_out <= 128 (others: NVC_ERR_UNSUPPORTED). */
+int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
+              const float* pos, int64_t n, void* vis, int32_t vis_dtype, void* stream);
+
+/* Light selection by weighted reservoir sampling (Sec. 1, Sec. 3.1) and
+ * neural direct illumination (Sec. 3.2).
+ * vis: [n][m] in vis_dtype; pos: float32 [n][3] in scene units; nrm:
+ * float32 [n][3] unit normals or NULL (then the cosine term is dropped);
+ * lights: float32 [m][4] = (x, y, z, intensity); 1 <= m <= 128.
+ * Light weight w_i = f_i * max(v_i, vis_floor) (vis_floor = 0.001 keeps the
+ * sampler unbiased; 0 gives the biased variant), with the Lambertian
+ * unshadowed contribution, evaluated in FP32 in this order:
+ *   d = l - p; d2 = max((dx*dx + dy*dy) + dz*dz, 1e-6);
+ *   with normals: nd = (nx*dx + ny*dy) + nz*dz, f = (I * max(nd, 0)) / (d2 * sqrt(d2));
+ *   without:      f = I / d2.
+ * One uniform per pixel u = (r0 >> 8) * 2^-24 where r0 is the first word of
+ * Philox4x32-10 with counter (pixel lo32, pixel hi32, frame, 0) and key
+ * (seed lo32, seed hi32).  With C_i the sequential FP32 running sum of w in
+ * light order and W = C_{m-1}: idx = the first i with C_i > u * W.
+ * Outputs (float32 / int32 [n]): idx (-1 when W = 0), pmf = w_idx / W (0 when
+ * W = 0), wsum = W, and, if di != NULL, di = sum_i v_i f_i / pi (raw v). */
+int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m,
+                   const float* pos, const float* nrm, const float* lights, float vis_floor,
+                   uint64_t seed, uint32_t frame,
+                   int32_t* idx, float* pmf, float* wsum, float* di, void* stream);
+
+/* Training-pixel selection (Sec. 3.4: random screen-space positions).
+ * pix[b] = (r0 * n_pix) >> 32, r0 the first word of Philox4x32-10 with
+ * counter (b lo32, b hi32, frame, 1) and key (seed lo32, seed hi32):
+ * uniform with replacement over [0, n_pix).  pix: int32 [batch];
+ * 1 <= n_pix < 2^31. */
+int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch,
+                      int32_t* pix, void* stream);
+
+/* Shadow-ray labels (Sec. 3.4: one shadow ray from each training point to
+ * each light) against sphere occluders.  Sample b uses position
+ * pos[pix[b]] (pix may be NULL: pos[b]); pos: float32 scene units [*][3];
+ * lights: float32 [m][4]; spheres: float32 [n_spheres][4] = (cx, cy, cz, r).
+ * labels: uint8 [n][m], 1 = visible, 0 = occluded.  A ray p -> l is occluded
+ * when a sphere comes closer than r to the segment, decided in FP32 as
+ *   o = c - p, cc = ((ox*ox + oy*oy) + oz*oz) - r*r, d = l - p,
+ *   dd = (dx*dx + dy*dy) + dz*dz, b = (ox*dx + oy*dy) + oz*dz;
+ *   b <= 0: cc < 0;  b >= dd: |c - l|^2 < r*r;  otherwise cc*dd < b*b.
+ * 1 <= m <= 128; 0 <= n_spheres <= 4096. */
+int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n,
+                      const float* lights, int32_t m, const float* spheres, int32_t n_spheres,
+                      uint8_t* labels, void* stream);
+
+/* Host only.  Workspace bytes nvc_train_step needs for this network and batch. */
+int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch);
+
+/* One training pass (Sec. 3.3-3.4): re-encode and re-run the network on the
+ * batch (activations are recomputed, never stored to memory), take the loss
+ * gradient at the output, backpropagate through the MLP on the matrix cores,
+ * and scatter the encoding gradient into the hash table with FP32 atomics.
+ * Sample b uses unit-cube position pos[pix[b]] (pix may be NULL: pos[b]).
+ * Mode A (labels != NULL, dvis == NULL): loss over the batch of
+ *   NVC_LOSS_BCE: mean over batch*n_out of softplus(z) - y z,
+ *   NVC_LOSS_L2:  mean of (sigmoid(z) - y)^2;
+ *   labels: uint8 [batch][n_out] (0/1); *loss_out (if not NULL) = the loss.
+ * Mode B (labels == NULL, dvis != NULL): dvis float32 [batch][n_out] is an
+ *   upstream gradient dL/dv; loss_out is left untouched.
+ * grad_scale > 0 multiplies the output gradient before the low-precision
+ * backward and divides the results afterwards (loss scaling; exact in
+ * real arithmetic).  0 selects the default (batch*n_out in mode A, 1 in B).
+ * Gradients are ADDED to g_table (float32 [L][T][F]) and g_w (float32,
+ * master-weight layout); the caller zeroes them (nvc_adam can).  Table
+ * atomics make g_table's rounding order nondeterministic.
+ * workspace: nvc_train_workspace_bytes bytes of device memory. */
+int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
+                   const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                   const uint8_t* labels, const float* dvis, int32_t loss, float grad_scale,
+                   float* g_table, float* g_w, float* loss_out,
+                   void* workspace, int64_t workspace_bytes, void* stream);
+
+/* One Adam step (Sec. 3.4; Kingma & Ba) over `count` FP32 parameters, dense:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)
+ * step >= 1 counts from 1.  If zero_grad != 0, g is set to 0 afterwards
+ * (the next nvc_train_step then accumulates into a clean buffer). */
+int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step,
+             float lr, float beta1, float beta2, float eps, int32_t zero_grad, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NVC_H */

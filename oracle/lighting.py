@@ -24,7 +24,8 @@ with this exact operation order:
     d   = l - p                       (componentwise)
     d2  = max((dx*dx + dy*dy) + dz*dz, 1e-6)
     nd  = (nx*dx + ny*dy) + nz*dz     (with normals)
-    f   = (I * (max(nd, 0) / sqrt(d2))) / d2   or   I / d2 without normals
+    f   = (I * max(nd, 0)) / (d2 * sqrt(d2))   or   I / d2 without normals
+          (n . w / d^2 with w = d / |d|, i.e. I * cos / d^2)
     w   = f * max(v, floor)
     C_i = C_{i-1} + w_i  (sequential, light order);  t = u * W
 """
@@ -51,8 +52,7 @@ def unshadowed_weight(pos, nrm, lights, dtype=np.float64) -> np.ndarray:
         return inten / d2
     n = np.asarray(nrm).astype(dtype)
     nd = (n[:, None, 0] * dx + n[:, None, 1] * dy) + n[:, None, 2] * dz
-    cosv = np.fmax(nd, dt(0.0)) / np.sqrt(d2)
-    return (inten * cosv) / d2
+    return (inten * np.fmax(nd, dt(0.0))) / (d2 * np.sqrt(d2))
 
 
 def clamp_visibility(vis, floor: float = VIS_FLOOR, dtype=np.float64) -> np.ndarray:

@@ -1,0 +1,191 @@
+"""Python binding of include/nvc.h on torch tensors: argument marshalling only.
+
+Each function has the name of the C entry point it calls, checks that tensors
+live on the GPU with the expected dtype, shape and contiguity, passes their
+device pointers and the current HIP stream, and raises NvcError on a
+negative status.  All computation happens in the HIP kernels of libnvc.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import NvcGrid, NvcMlp, NVC_F32, NVC_F16, NVC_BF16
+
+_DT_CODE = {torch.float32: NVC_F32, torch.float16: NVC_F16, torch.bfloat16: NVC_BF16}
+_DT_TORCH = {v: k for k, v in _DT_CODE.items()}
+DTYPES = {"f32": NVC_F32, "f16": NVC_F16, "bf16": NVC_BF16}
+
+
+def dtype_code(x) -> int:
+    if isinstance(x, str):
+        return DTYPES[x]
+    if isinstance(x, torch.dtype):
+        return _DT_CODE[x]
+    return int(x)
+
+
+def torch_dtype(code: int) -> torch.dtype:
+    return _DT_TORCH[code]
+
+
+def make_grid(n_levels, n_feat, log2_T, base_res, growth) -> NvcGrid:
+    return NvcGrid(int(n_levels), int(n_feat), int(log2_T), int(base_res), float(growth))
+
+
+def make_mlp(n_in, width, n_hidden, n_out, act="relu", leaky_slope=0.01, dtype="f16") -> NvcMlp:
+    act_code = {"relu": _lib.NVC_ACT_RELU, "leaky": _lib.NVC_ACT_LEAKY}[act] if isinstance(act, str) else int(act)
+    return NvcMlp(int(n_in), int(width), int(n_hidden), int(n_out), act_code, float(leaky_slope), dtype_code(dtype))
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t, name, dtype=None, shape=None, optional=False):
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if shape is not None:
+        if t.dim() != len(shape) or any(s is not None and a != s for a, s in zip(t.shape, shape)):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    return t.data_ptr()
+
+
+def nvc_version() -> int:
+    return _lib.load().nvc_version()
+
+
+def nvc_grid_levels(grid: NvcGrid):
+    L = _lib.load()
+    res = (ctypes.c_int32 * grid.n_levels)()
+    dense = (ctypes.c_int32 * grid.n_levels)()
+    _lib.check("nvc_grid_levels", L.nvc_grid_levels(ctypes.byref(grid), res, dense))
+    return list(res), [bool(d) for d in dense]
+
+
+def nvc_mlp_param_count(mlp: NvcMlp) -> int:
+    return _lib.check("nvc_mlp_param_count", _lib.load().nvc_mlp_param_count(ctypes.byref(mlp)))
+
+
+def nvc_mlp_packed_bytes(mlp: NvcMlp) -> int:
+    return _lib.check("nvc_mlp_packed_bytes", _lib.load().nvc_mlp_packed_bytes(ctypes.byref(mlp)))
+
+
+def nvc_train_workspace_bytes(grid: NvcGrid, mlp: NvcMlp, batch: int) -> int:
+    return _lib.check("nvc_train_workspace_bytes",
+                      _lib.load().nvc_train_workspace_bytes(ctypes.byref(grid), ctypes.byref(mlp), int(batch)))
+
+
+def nvc_pack_mlp(mlp: NvcMlp, w: torch.Tensor, packed: torch.Tensor, stream=None) -> None:
+    n = nvc_mlp_param_count(mlp)
+    pw = _ptr(w, "w", torch.float32, (n,))
+    if packed.numel() * packed.element_size() < nvc_mlp_packed_bytes(mlp):
+        raise ValueError("packed buffer too small")
+    pp = _ptr(packed, "packed")
+    _lib.check("nvc_pack_mlp", _lib.load().nvc_pack_mlp(ctypes.byref(mlp), pw, pp, _stream(stream)))
+
+
+def nvc_encode(grid: NvcGrid, table: torch.Tensor, pos: torch.Tensor, enc: torch.Tensor, stream=None) -> None:
+    n = pos.shape[0]
+    L, F = grid.n_levels, grid.n_feat
+    pt = _ptr(table, "table", torch.float32, (L, 1 << grid.log2_T, F))
+    pp = _ptr(pos, "pos", torch.float32, (n, 3))
+    pe = _ptr(enc, "enc", (torch.float32, torch.float16, torch.bfloat16), (n, L * F))
+    _lib.check("nvc_encode", _lib.load().nvc_encode(ctypes.byref(grid), pt, pp, n, pe, _DT_CODE[enc.dtype],
+                                                    _stream(stream)))
+
+
+def nvc_infer(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor,
+              vis: torch.Tensor, stream=None) -> None:
+    n = pos.shape[0]
+    pt = _ptr(table, "table", torch.float32, (grid.n_levels, 1 << grid.log2_T, grid.n_feat))
+    pk = _ptr(packed, "packed")
+    pp = _ptr(pos, "pos", torch.float32, (n, 3))
+    pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16), (n, mlp.n_out))
+    _lib.check("nvc_infer", _lib.load().nvc_infer(ctypes.byref(grid), ctypes.byref(mlp), pt, pk, pp, n, pv,
+                                                  _DT_CODE[vis.dtype], _stream(stream)))
+
+
+def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, vis_floor: float, seed: int,
+                   frame: int, idx: torch.Tensor, pmf: torch.Tensor, wsum: torch.Tensor, di=None,
+                   stream=None) -> None:
+    n, m = vis.shape
+    pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16))
+    pp = _ptr(pos, "pos", torch.float32, (n, 3))
+    pn = _ptr(nrm, "nrm", torch.float32, (n, 3), optional=True)
+    pl = _ptr(lights, "lights", torch.float32, (m, 4))
+    pi = _ptr(idx, "idx", torch.int32, (n,))
+    pm = _ptr(pmf, "pmf", torch.float32, (n,))
+    pw = _ptr(wsum, "wsum", torch.float32, (n,))
+    pd = _ptr(di, "di", torch.float32, (n,), optional=True)
+    _lib.check("nvc_sample_wrs", _lib.load().nvc_sample_wrs(pv, _DT_CODE[vis.dtype], n, m, pp, pn, pl,
+                                                            float(vis_floor), int(seed) & (2 ** 64 - 1),
+                                                            int(frame) & 0xFFFFFFFF, pi, pm, pw, pd,
+                                                            _stream(stream)))
+
+
+def nvc_select_pixels(seed: int, frame: int, n_pix: int, pix: torch.Tensor, stream=None) -> None:
+    pp = _ptr(pix, "pix", torch.int32)
+    _lib.check("nvc_select_pixels", _lib.load().nvc_select_pixels(int(seed) & (2 ** 64 - 1),
+                                                                  int(frame) & 0xFFFFFFFF, int(n_pix),
+                                                                  pix.numel(), pp, _stream(stream)))
+
+
+def nvc_shadow_labels(pos: torch.Tensor, pix, lights: torch.Tensor, spheres: torch.Tensor, labels: torch.Tensor,
+                      stream=None) -> None:
+    n, m = labels.shape
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    px = _ptr(pix, "pix", torch.int32, (n,), optional=True)
+    if pix is None and pos.shape[0] < n:
+        raise ValueError("pos has fewer rows than labels")
+    pl = _ptr(lights, "lights", torch.float32, (m, 4))
+    ps = _ptr(spheres, "spheres", torch.float32, (None, 4)) if spheres.numel() else None
+    pb = _ptr(labels, "labels", torch.uint8)
+    _lib.check("nvc_shadow_labels", _lib.load().nvc_shadow_labels(pp, px, n, pl, m, ps, spheres.shape[0], pb,
+                                                                  _stream(stream)))
+
+
+def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor, pix,
+                   batch: int, labels, dvis, loss: int, grad_scale: float, g_table: torch.Tensor,
+                   g_w: torch.Tensor, loss_out, workspace: torch.Tensor, stream=None) -> None:
+    tshape = (grid.n_levels, 1 << grid.log2_T, grid.n_feat)
+    pt = _ptr(table, "table", torch.float32, tshape)
+    pk = _ptr(packed, "packed")
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    px = _ptr(pix, "pix", torch.int32, (batch,), optional=True)
+    if pix is None and pos.shape[0] < batch:
+        raise ValueError("pos has fewer rows than the batch")
+    pl = _ptr(labels, "labels", torch.uint8, (batch, mlp.n_out), optional=True)
+    pd = _ptr(dvis, "dvis", torch.float32, (batch, mlp.n_out), optional=True)
+    pg = _ptr(g_table, "g_table", torch.float32, tshape)
+    pw = _ptr(g_w, "g_w", torch.float32, (nvc_mlp_param_count(mlp),))
+    po = _ptr(loss_out, "loss_out", torch.float32, (1,), optional=True)
+    pws = _ptr(workspace, "workspace")
+    wsb = workspace.numel() * workspace.element_size()
+    _lib.check("nvc_train_step", _lib.load().nvc_train_step(ctypes.byref(grid), ctypes.byref(mlp), pt, pk, pp, px,
+                                                            int(batch), pl, pd, int(loss), float(grad_scale), pg,
+                                                            pw, po, pws, wsb, _stream(stream)))
+
+
+def nvc_adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
+             beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None) -> None:
+    n = p.numel()
+    ptrs = [_ptr(t, name, torch.float32) for t, name in ((p, "p"), (g, "g"), (m, "m"), (v, "v"))]
+    if any(t.numel() != n for t in (g, m, v)):
+        raise ValueError("p, g, m, v must have the same number of elements")
+    _lib.check("nvc_adam", _lib.load().nvc_adam(*ptrs, n, int(step), float(lr), float(beta1), float(beta2),
+                                                float(eps), int(bool(zero_grad)), _stream(stream)))

@@ -1,0 +1,182 @@
+"""The neural visibility cache as a stateful object, and its autograd wrapper.
+
+`NVCache` owns the device tensors of one cache (hash table, FP32 master
+weights, packed low-precision weights, Adam moments, gradient buffers,
+training workspace) and strings the C-ABI calls together:
+
+  infer    encoding + MLP -> visibility per light        (Sec. 3.1 steps 1-2)
+  sample   WRS light pick + neural DI                    (Sec. 3.1 step 3, Sec. 3.2)
+  train    pixel pick, shadow labels, gradients, Adam    (Sec. 3.4)
+  frame    one frame: sample on every pixel, then train  (Sec. 4, passes 2-4)
+
+torch is used for device memory and the stream only; every step runs in
+libnvc.so.  `NVCFunction` exposes inference to torch autograd with the
+library's own backward (the training kernel in upstream-gradient mode).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import api
+from ._lib import NVC_LOSS_BCE, NVC_LOSS_L2
+
+
+class NVCache:
+    def __init__(self, grid_cfg, mlp_cfg, table, weights, device="cuda", seed: int = 2, lr: float = 1e-2,
+                 beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8, loss: str = "bce",
+                 vis_floor: float = 1e-3, max_batch: int = 0):
+        self.grid = api.make_grid(grid_cfg.n_levels, grid_cfg.n_feat, grid_cfg.log2_T, grid_cfg.base_res,
+                                  grid_cfg.growth)
+        self.mlp = api.make_mlp(mlp_cfg.n_in, mlp_cfg.width, mlp_cfg.n_hidden, mlp_cfg.n_out, mlp_cfg.act,
+                                mlp_cfg.leaky_slope, mlp_cfg.dtype)
+        self.device = torch.device(device)
+        self.vis_dtype = api.torch_dtype(self.mlp.dtype)
+        self.seed = int(seed)
+        self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.loss = {"bce": NVC_LOSS_BCE, "l2": NVC_LOSS_L2}[loss]
+        self.vis_floor = vis_floor
+        self.table = torch.as_tensor(np.ascontiguousarray(table), dtype=torch.float32).to(self.device)
+        flat = np.concatenate([np.asarray(w, np.float32).reshape(-1) for w in weights]) \
+            if isinstance(weights, (list, tuple)) else np.asarray(weights, np.float32)
+        self.w = torch.as_tensor(flat, dtype=torch.float32).to(self.device).contiguous()
+        if self.w.numel() != api.nvc_mlp_param_count(self.mlp):
+            raise ValueError("weight count does not match the network shape")
+        self.packed = torch.empty(api.nvc_mlp_packed_bytes(self.mlp), dtype=torch.uint8, device=self.device)
+        self.m_table = torch.zeros_like(self.table)
+        self.v_table = torch.zeros_like(self.table)
+        self.g_table = torch.zeros_like(self.table)
+        self.m_w = torch.zeros_like(self.w)
+        self.v_w = torch.zeros_like(self.w)
+        self.g_w = torch.zeros_like(self.w)
+        self.loss_buf = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.step = 0
+        self.workspace = None
+        self._ws_batch = 0
+        if max_batch:
+            self._ensure_workspace(max_batch)
+        self.pack()
+
+    # ------------------------------------------------------------ plumbing
+    def _ensure_workspace(self, batch: int):
+        need = api.nvc_train_workspace_bytes(self.grid, self.mlp, batch)
+        if self.workspace is None or self.workspace.numel() < need:
+            self.workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        self._ws_batch = max(self._ws_batch, batch)
+
+    def pack(self, stream=None):
+        api.nvc_pack_mlp(self.mlp, self.w, self.packed, stream)
+
+    # ------------------------------------------------------------ inference and sampling
+    def infer(self, pos_unit: torch.Tensor, vis: torch.Tensor | None = None, dtype=None, stream=None) -> torch.Tensor:
+        if vis is None:
+            vis = torch.empty((pos_unit.shape[0], self.mlp.n_out), dtype=dtype or self.vis_dtype, device=self.device)
+        api.nvc_infer(self.grid, self.mlp, self.table, self.packed, pos_unit, vis, stream)
+        return vis
+
+    def encode(self, pos_unit: torch.Tensor, dtype=torch.float32, stream=None) -> torch.Tensor:
+        enc = torch.empty((pos_unit.shape[0], self.grid.n_levels * self.grid.n_feat), dtype=dtype,
+                          device=self.device)
+        api.nvc_encode(self.grid, self.table, pos_unit, enc, stream)
+        return enc
+
+    def sample(self, vis, pos, nrm, lights, frame: int, out: dict | None = None, with_di: bool = True,
+               stream=None) -> dict:
+        n = vis.shape[0]
+        if out is None:
+            out = {"idx": torch.empty(n, dtype=torch.int32, device=self.device),
+                   "pmf": torch.empty(n, dtype=torch.float32, device=self.device),
+                   "wsum": torch.empty(n, dtype=torch.float32, device=self.device),
+                   "di": torch.empty(n, dtype=torch.float32, device=self.device) if with_di else None}
+        api.nvc_sample_wrs(vis, pos, nrm, lights, self.vis_floor, self.seed, frame, out["idx"], out["pmf"],
+                           out["wsum"], out.get("di"), stream)
+        return out
+
+    # ------------------------------------------------------------ training
+    def gradients(self, pos_unit, labels=None, dvis=None, pix=None, batch: int | None = None,
+                  grad_scale: float = 0.0, stream=None):
+        """Accumulate the gradients of one batch into g_table / g_w (and the loss into loss_buf)."""
+        if batch is None:
+            batch = pix.shape[0] if pix is not None else pos_unit.shape[0]
+        self._ensure_workspace(batch)
+        api.nvc_train_step(self.grid, self.mlp, self.table, self.packed, pos_unit, pix, batch, labels, dvis,
+                           self.loss, grad_scale, self.g_table, self.g_w, self.loss_buf if labels is not None else None,
+                           self.workspace, stream)
+
+    def adam(self, stream=None):
+        """One Adam step on table and weights (gradients cleared), then repack the weights."""
+        self.step += 1
+        api.nvc_adam(self.table, self.g_table, self.m_table, self.v_table, self.step, self.lr, self.beta1,
+                     self.beta2, self.eps, True, stream)
+        api.nvc_adam(self.w, self.g_w, self.m_w, self.v_w, self.step, self.lr, self.beta1, self.beta2, self.eps,
+                     True, stream)
+        self.pack(stream)
+
+    def train_step(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
+                   stream=None) -> dict:
+        """Pick `batch` pixels, label them with shadow rays, one gradient pass and one Adam step."""
+        if bufs is None:
+            bufs = {"pix": torch.empty(batch, dtype=torch.int32, device=self.device),
+                    "labels": torch.empty((batch, self.mlp.n_out), dtype=torch.uint8, device=self.device)}
+        api.nvc_select_pixels(self.seed, frame, pos_unit.shape[0], bufs["pix"], stream)
+        api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
+        self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
+        self.adam(stream)
+        return bufs
+
+    def frame(self, pos_unit, pos_scene, nrm, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
+              stream=None) -> dict:
+        """Inference + WRS + neural DI on every pixel, then one training step."""
+        if bufs is None:
+            n = pos_unit.shape[0]
+            bufs = {"vis": torch.empty((n, self.mlp.n_out), dtype=self.vis_dtype, device=self.device)}
+        self.infer(pos_unit, bufs["vis"], stream=stream)
+        bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=stream)
+        bufs["train"] = self.train_step(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
+                                        stream=stream)
+        return bufs
+
+    # ------------------------------------------------------------ checkpoint
+    def state_dict(self) -> dict:
+        return {"table": self.table.detach().cpu(), "w": self.w.detach().cpu(),
+                "m_table": self.m_table.cpu(), "v_table": self.v_table.cpu(), "m_w": self.m_w.cpu(),
+                "v_w": self.v_w.cpu(), "step": self.step, "seed": self.seed}
+
+    def load_state_dict(self, sd: dict):
+        for k in ("table", "w", "m_table", "v_table", "m_w", "v_w"):
+            getattr(self, k).copy_(sd[k].to(self.device))
+        self.step = int(sd["step"])
+        self.seed = int(sd["seed"])
+        self.g_table.zero_()
+        self.g_w.zero_()
+        self.pack()
+
+
+class NVCFunction(torch.autograd.Function):
+    """vis = sigmoid(MLP(encode(pos))) with gradients for the table and the FP32 master weights.
+
+    forward packs `w` and runs nvc_infer (FP32 output); backward runs
+    nvc_train_step with the upstream gradient, recomputing the activations.
+    """
+
+    @staticmethod
+    def forward(ctx, pos_unit, table, w, cache: NVCache, grad_scale: float = 0.0):
+        api.nvc_pack_mlp(cache.mlp, w.detach().contiguous(), cache.packed)
+        vis = torch.empty((pos_unit.shape[0], cache.mlp.n_out), dtype=torch.float32, device=pos_unit.device)
+        api.nvc_infer(cache.grid, cache.mlp, table.detach().contiguous(), cache.packed, pos_unit, vis)
+        ctx.save_for_backward(pos_unit, table, w)
+        ctx.cache = cache
+        ctx.grad_scale = grad_scale
+        return vis
+
+    @staticmethod
+    def backward(ctx, dvis):
+        pos_unit, table, w = ctx.saved_tensors
+        cache = ctx.cache
+        g_table = torch.zeros_like(table)
+        g_w = torch.zeros_like(w)
+        cache._ensure_workspace(pos_unit.shape[0])
+        api.nvc_train_step(cache.grid, cache.mlp, table.detach().contiguous(), cache.packed, pos_unit, None,
+                           pos_unit.shape[0], None, dvis.contiguous().float(), cache.loss, ctx.grad_scale,
+                           g_table, g_w, None, cache.workspace)
+        return None, g_table, g_w, None, None

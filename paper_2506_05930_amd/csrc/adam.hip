@@ -1,0 +1,59 @@
+// Dense Adam step (Sec. 3.4; Kingma & Ba 2015) over FP32 parameters, with the
+// optional clearing of the gradient fused into the same pass (one read and
+// one write of every array: 32 bytes per parameter).
+#include <hip/hip_runtime.h>
+
+#include "nvc_internal.hpp"
+
+namespace nvc {
+
+__device__ inline void adam_one(float& p, float& g, float& m, float& v, float step_size, float bc2_sqrt, float b1,
+                                float b2, float eps) {
+    m = b1 * m + (1.0f - b1) * g;
+    v = b2 * v + (1.0f - b2) * (g * g);
+    const float denom = __fsqrt_rn(v) / bc2_sqrt + eps;
+    p = p - step_size * (m / denom);
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
+                                                   float* __restrict__ v, int64_t count, float step_size,
+                                                   float bc2_sqrt, float b1, float b2, float eps, int zero_grad,
+                                                   int aligned) {
+    const int64_t n4 = aligned ? count / 4 : 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        float4 P = reinterpret_cast<float4*>(p)[i];
+        float4 Gr = reinterpret_cast<float4*>(g)[i];
+        float4 Mm = reinterpret_cast<float4*>(m)[i];
+        float4 V = reinterpret_cast<float4*>(v)[i];
+        adam_one(P.x, Gr.x, Mm.x, V.x, step_size, bc2_sqrt, b1, b2, eps);
+        adam_one(P.y, Gr.y, Mm.y, V.y, step_size, bc2_sqrt, b1, b2, eps);
+        adam_one(P.z, Gr.z, Mm.z, V.z, step_size, bc2_sqrt, b1, b2, eps);
+        adam_one(P.w, Gr.w, Mm.w, V.w, step_size, bc2_sqrt, b1, b2, eps);
+        reinterpret_cast<float4*>(p)[i] = P;
+        reinterpret_cast<float4*>(m)[i] = Mm;
+        reinterpret_cast<float4*>(v)[i] = V;
+        if (zero_grad) reinterpret_cast<float4*>(g)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        adam_one(p[i], g[i], m[i], v[i], step_size, bc2_sqrt, b1, b2, eps);
+        if (zero_grad) g[i] = 0.0f;
+    }
+}
+
+int cu_count();
+
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, float step_size, float bc2_sqrt,
+                       float beta1, float beta2, float eps, int zero_grad, hipStream_t st) {
+    const int64_t n4 = (count + 3) / 4;
+    int64_t blocks = (n4 + 255) / 256;
+    const int64_t cap = (int64_t)cu_count() * 8;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    const int aligned = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15u) == 0;
+    adam_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, count, step_size, bc2_sqrt, beta1, beta2, eps,
+                                                 zero_grad, aligned);
+    return hipGetLastError();
+}
+
+}  // namespace nvc

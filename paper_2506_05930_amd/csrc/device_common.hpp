@@ -1,0 +1,248 @@
+// Device-side building blocks shared by the cache's kernels (gfx950 / CDNA4).
+//
+// Matrix-core tiling.  Every MLP layer is computed transposed, as
+//     D[neuron][point] = sum_k W[neuron][k] * H[k][point]
+// on 16x16 output tiles (16 neurons x 16 points) with
+//   v_mfma_f32_16x16x32_{f16,bf16}  (K = 32 per instruction, 8 K-values per lane)
+//   v_mfma_f32_16x16x4_f32          (K = 4, 1 K-value per lane)
+// Lane l of a wave64 holds, for operand A, row l%16 and K-slots 8*(l/16)..+7
+// (f32: K-slot l/16); for operand B, column l%16 and the same K-slots; for the
+// accumulator, column l%16 and rows 4*(l/16)+i, i < 4.
+//
+// The accumulator of one layer therefore leaves lane l with point l%16 and
+// neurons 16*b + 4*g + i (g = l/16) of every 16-neuron block b.  The next
+// layer consumes exactly those values as its B operand without any data
+// movement, by numbering the K dimension to match:
+//   f16/bf16: K-chunk c, lane group g, slot s  ->  neuron 32c + 4g + s        (s < 4)
+//                                                  neuron 32c + 16 + 4g + s-4 (s >= 4)
+//   f32:      K-chunk c = 4b + i, lane group g  ->  neuron 16b + 4g + i
+// The weight fragments (operand A) are packed on the host side with the same
+// numbering, so activations stay in registers from the encoding to the
+// sigmoid.  The same holds for the backward pass with the transposed weights.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nvc_internal.hpp"
+
+namespace nvc {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// --------------------------------------------------------------- dtypes
+template <int DT> struct Mma;
+
+template <> struct Mma<DT_F16> {
+    using elem = _Float16;
+    using frag = half8_t;
+    static constexpr int EPL = 8;      // K values per lane per instruction
+    static constexpr int KSTEP = 32;   // K per instruction
+    static constexpr int PADK = 32;    // K padding granule (two 16-neuron blocks)
+    __device__ static inline float4_t mma(frag a, frag b, float4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline elem cvt(float x) { return (elem)x; }
+};
+
+template <> struct Mma<DT_BF16> {
+    using elem = __bf16;
+    using frag = bf16x8_t;
+    static constexpr int EPL = 8;
+    static constexpr int KSTEP = 32;
+    static constexpr int PADK = 32;
+    __device__ static inline float4_t mma(frag a, frag b, float4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline elem cvt(float x) { return (elem)x; }
+};
+
+template <> struct Mma<DT_F32> {
+    using elem = float;
+    using frag = float;
+    static constexpr int EPL = 1;
+    static constexpr int KSTEP = 4;
+    static constexpr int PADK = 16;
+    __device__ static inline float4_t mma(frag a, frag b, float4_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline elem cvt(float x) { return x; }
+};
+
+template <int DT> __device__ inline float to_f32(typename Mma<DT>::elem x) { return (float)x; }
+
+// Number of K-chunks covering NB 16-neuron blocks (NB already padded to PADK/16).
+template <int DT> __host__ __device__ constexpr int kchunks(int nb) {
+    return DT == DT_F32 ? nb * 4 : nb / 2;
+}
+
+// Neuron number of (chunk kc, lane group g, slot s), see the file comment.
+template <int DT> __host__ __device__ constexpr int kperm(int kc, int g, int s) {
+    return DT == DT_F32 ? 16 * (kc / 4) + 4 * g + (kc % 4)
+                        : 32 * kc + (s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4));
+}
+
+// B operand for chunk kc from a lane's register activations act[block][i].
+template <int DT, int NB>
+__device__ inline typename Mma<DT>::frag make_frag(const float (&act)[NB][4], int kc) {
+    typename Mma<DT>::frag f;
+    if constexpr (DT == DT_F32) {
+        f = act[kc / 4][kc % 4];
+    } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) f[s] = Mma<DT>::cvt(act[2 * kc + s / 4][s % 4]);
+    }
+    return f;
+}
+
+// A operand fragment (ob, kc) of a packed matrix with KC chunks per row block.
+template <int DT>
+__device__ inline typename Mma<DT>::frag load_frag(const typename Mma<DT>::elem* base, int ob, int kc, int KC,
+                                                   int lane) {
+    using M = Mma<DT>;
+    const typename M::elem* p = base + ((size_t)(ob * KC + kc) * 64 + lane) * M::EPL;
+    return *reinterpret_cast<const typename M::frag*>(p);
+}
+
+// --------------------------------------------------------------- Philox4x32-10
+// Salmon et al. 2011: ten rounds of two 32x32->64 multiplies; high halves are
+// mixed with the other counter words and the round key; Weyl key schedule.
+__device__ inline uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return c0;
+}
+
+// --------------------------------------------------------------- hash grid
+struct GridDev {
+    int32_t n_levels;
+    int32_t n_feat;
+    uint32_t T;
+    uint32_t dense_mask;          // bit l: level l stored densely
+    int32_t res[kMaxLevels];      // N_l
+};
+
+__device__ inline float clamp_unit(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+
+// Cell, fraction and table indices of the 8 corners of a position at level l.
+// Corner k = (k&1, (k>>1)&1, (k>>2)&1).  Decided in FP32: s = fl32(x * N).
+struct Corners {
+    uint32_t idx[8];
+    float w[8];
+};
+
+__device__ inline void level_corners(const GridDev& g, int l, float x, float y, float z, Corners& c) {
+    const int N = g.res[l];
+    const float Nf = (float)N;                          // exact, N < 2^24
+    const float sx = x * Nf, sy = y * Nf, sz = z * Nf;
+    const int cx = min((int)floorf(sx), N - 1);
+    const int cy = min((int)floorf(sy), N - 1);
+    const int cz = min((int)floorf(sz), N - 1);
+    const float fx = sx - (float)cx, fy = sy - (float)cy, fz = sz - (float)cz;   // exact
+    if ((g.dense_mask >> l) & 1u) {
+        const uint32_t n1 = (uint32_t)N + 1u;
+        const uint32_t b = (uint32_t)cx + n1 * ((uint32_t)cy + n1 * (uint32_t)cz);
+        const uint32_t sy1 = n1, sz1 = n1 * n1;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c.idx[k] = b + ((k & 1) ? 1u : 0u) + ((k & 2) ? sy1 : 0u) + ((k & 4) ? sz1 : 0u);
+    } else {
+        const uint32_t mask = g.T - 1u;
+        const uint32_t hx0 = (uint32_t)cx, hx1 = (uint32_t)cx + 1u;
+        const uint32_t hy0 = (uint32_t)cy * 2654435761u, hy1 = ((uint32_t)cy + 1u) * 2654435761u;
+        const uint32_t hz0 = (uint32_t)cz * 805459861u, hz1 = ((uint32_t)cz + 1u) * 805459861u;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            c.idx[k] = (((k & 1) ? hx1 : hx0) ^ ((k & 2) ? hy1 : hy0) ^ ((k & 4) ? hz1 : hz0)) & mask;
+    }
+    const float wx[2] = {1.0f - fx, fx}, wy[2] = {1.0f - fy, fy}, wz[2] = {1.0f - fz, fz};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c.w[k] = (wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1];
+}
+
+// F features of level l at a (clamped) position: sum over corners of w * table[l][idx][j].
+template <int F>
+__device__ inline void encode_level(const float* __restrict__ table, const GridDev& g, int l, float x, float y,
+                                    float z, float (&out)[F]) {
+    Corners c;
+    level_corners(g, l, x, y, z, c);
+    const float* base = table + (size_t)l * g.T * F;
+#pragma unroll
+    for (int j = 0; j < F; ++j) out[j] = 0.0f;
+    if constexpr (F == 2) {
+        float2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = *reinterpret_cast<const float2*>(base + (size_t)c.idx[k] * 2);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            out[0] = fmaf(c.w[k], v[k].x, out[0]);
+            out[1] = fmaf(c.w[k], v[k].y, out[1]);
+        }
+    } else if constexpr (F == 4) {
+        float4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = *reinterpret_cast<const float4*>(base + (size_t)c.idx[k] * 4);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            out[0] = fmaf(c.w[k], v[k].x, out[0]);
+            out[1] = fmaf(c.w[k], v[k].y, out[1]);
+            out[2] = fmaf(c.w[k], v[k].z, out[2]);
+            out[3] = fmaf(c.w[k], v[k].w, out[3]);
+        }
+    } else {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = base[c.idx[k]];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) out[0] = fmaf(c.w[k], v[k], out[0]);
+    }
+}
+
+// The encoding features a lane owns in the MLP operand layout: for each input
+// 16-block b, features 16b + 4g + i (i < 4) where g = lane/16.  Features past
+// n_levels*F are zero.  Result is act[b][i].
+template <int F, int NINB>
+__device__ inline void encode_lane(const float* __restrict__ table, const GridDev& g, int grp, float x, float y,
+                                   float z, float (&act)[NINB][4]) {
+    static_assert(F == 1 || F == 2 || F == 4, "features per level");
+#pragma unroll
+    for (int b = 0; b < NINB; ++b) {
+#pragma unroll
+        for (int q = 0; q < 4; q += F) {
+            const int feat = 16 * b + 4 * grp + q;
+            const int l = feat / F;
+            float v[F];
+            if (l < g.n_levels) {
+                encode_level<F>(table, g, l, x, y, z, v);
+            } else {
+#pragma unroll
+                for (int j = 0; j < F; ++j) v[j] = 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < F; ++j) act[b][q + j] = v[j];
+        }
+    }
+}
+
+// Logistic function evaluated from the FP32 accumulator.
+__device__ inline float sigmoidf_(float z) {
+    if (z >= 0.0f) return 1.0f / (1.0f + expf(-z));
+    const float e = expf(z);
+    return e / (1.0f + e);
+}
+
+}  // namespace nvc

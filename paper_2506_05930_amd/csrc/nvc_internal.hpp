@@ -1,0 +1,77 @@
+// Internal declarations shared by the C-ABI layer and the kernel translation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+namespace nvc {
+
+constexpr int DT_F32 = 0;
+constexpr int DT_F16 = 1;
+constexpr int DT_BF16 = 2;
+constexpr int kMaxLevels = 32;
+
+// Host copy of the level table, passed to kernels by value.
+struct GridHost {
+    int32_t n_levels;
+    int32_t n_feat;
+    int32_t log2_T;
+    uint32_t dense_mask;
+    int32_t res[kMaxLevels];
+};
+
+// Network shape after padding to matrix-core granules.
+struct NetShape {
+    int dtype;
+    int n_in, width, n_hidden, n_out;
+    int act;              // 0 relu, 1 leaky
+    float slope;
+};
+
+// Packed-weight layout: per layer, the forward fragments then the transposed ones.
+struct LayerPack {
+    int in, out;              // logical sizes
+    int nb_out_f, kc_in_f;    // forward: 16-row blocks of `out`, K-chunks over `in`
+    int nb_in_b, kc_out_b;    // backward: 16-row blocks of `in`, K-chunks over `out`
+    int64_t off_f, off_b;     // element offsets into the packed buffer
+    int64_t w_off;            // float offset of this layer in the master weights
+};
+
+constexpr int kMaxLayers = 8;
+
+struct PackPlan {
+    int n_layers;
+    LayerPack layer[kMaxLayers];
+    int64_t total_elems;
+};
+
+PackPlan make_pack_plan(const NetShape& s);
+size_t dtype_size(int dt);
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_pack(const NetShape& s, const PackPlan& plan, const float* w, void* packed, hipStream_t st);
+hipError_t launch_encode(const GridHost& g, const float* table, const float* pos, int64_t n, void* enc,
+                         int enc_dtype, hipStream_t st);
+// Returns hipErrorNotSupported (without launching) if no kernel is built for this shape.
+hipError_t launch_infer(const GridHost& g, const NetShape& s, const PackPlan& plan, const float* table,
+                        const void* packed, const float* pos, int64_t n, void* vis, int vis_dtype, hipStream_t st);
+bool infer_supported(const GridHost& g, const NetShape& s);
+hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
+                      const float* lights, float vis_floor, uint64_t seed, uint32_t frame, int32_t* idx,
+                      float* pmf, float* wsum, float* di, hipStream_t st);
+hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix,
+                                hipStream_t st);
+hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
+                         const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st);
+bool train_supported(const GridHost& g, const NetShape& s);
+int64_t train_workspace_bytes(const GridHost& g, const NetShape& s, int64_t batch);
+hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& plan, const float* table,
+                        const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                        const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
+                        float* g_w, float* loss_out, void* workspace, hipStream_t st);
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, float step_size, float bc2_sqrt,
+                       float beta1, float beta2, float eps, int zero_grad, hipStream_t st);
+
+}  // namespace nvc

@@ -1,0 +1,497 @@
+// One training pass of the cache (Sec. 3.3-3.4): recompute the encoding and the
+// forward pass per tile (nothing is stored to memory), take the loss gradient
+// at the sigmoid output, backpropagate on the matrix cores, accumulate the
+// weight gradient across the block, and scatter the encoding gradient into
+// the hash table with FP32 atomics.
+//
+// Block = 4 waves; a wave handles 32 samples (two 16-point sub-tiles) per
+// iteration, a block 128.  For each layer k, from the output down:
+//   1. every wave writes its delta_k and the layer input h_k (both in the
+//      matrix-core dtype) to LDS as [neuron][sample];
+//   2. every wave computes delta_{k-1} = W_k^T delta_k * act'(h_k) in registers
+//      (the transposed weight fragments make it a plain matrix-core product);
+//   3. after a barrier, each wave adds its share of the 16x16 tiles of
+//      dW_k = delta_k h_k^T over the block's 128 samples into accumulators
+//      that live for the whole kernel;
+//   4. barrier.
+// At the end each block writes its partial dW to the workspace and a second
+// kernel reduces the partials (deterministic; no weight atomics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "device_common.hpp"
+#include "kernel_config.hpp"
+
+namespace nvc {
+
+GridDev grid_to_dev(const GridHost& g);
+
+template <int B, int E, class F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int kTrainWaves = 4;
+constexpr int kTrainSub = 2;                              // 16-point sub-tiles per wave
+constexpr int kTrainPts = 16 * kTrainSub * kTrainWaves;   // samples per block iteration
+
+struct TrainArgs {
+    GridDev g;
+    const float* table;
+    const void* packed;
+    int64_t off_f[kMaxLayers];
+    int64_t off_b[kMaxLayers];
+    int64_t w_off[kMaxLayers];
+    int lin[kMaxLayers];
+    int lout[kMaxLayers];
+    const float* pos;
+    const int32_t* pix;
+    int64_t batch;
+    int n_out;
+    const uint8_t* labels;
+    const float* dvis;
+    int loss;             // 0 bce, 1 l2
+    float out_mul;        // multiplies the output gradient before the low-precision backward
+    float final_mul;      // multiplies every gradient written out
+    float* g_table;
+    float* ws_w;          // [gridDim.x][n_w]
+    float* ws_loss;       // [gridDim.x]
+    int64_t n_w;
+    int act;
+    float slope;
+};
+
+template <class C>
+struct TrainShape {
+    static constexpr int DT = C::DT;
+    static constexpr int NL = C::NHID + 1;
+    static constexpr int PADB = DT == DT_F32 ? 1 : 2;      // K granule in 16-blocks
+    static constexpr int NOUTB_K = (C::NOUTB + PADB - 1) / PADB * PADB;
+    __host__ __device__ static constexpr int nbi(int k) { return k == 0 ? C::NINB : C::WB; }
+    __host__ __device__ static constexpr int nbo(int k) { return k == NL - 1 ? C::NOUTB : C::WB; }
+    __host__ __device__ static constexpr int nbo_k(int k) { return k == NL - 1 ? NOUTB_K : C::WB; }
+    __host__ __device__ static constexpr int tiles(int k) { return nbi(k) * nbo(k); }
+    __host__ __device__ static constexpr int owned(int k) { return (tiles(k) + kTrainWaves - 1) / kTrainWaves; }
+    __host__ __device__ static constexpr int acc_off(int k) {
+        int o = 0;
+        for (int j = 0; j < k; ++j) o += owned(j);
+        return o;
+    }
+    static constexpr int ACC = acc_off(NL);
+    static constexpr int RD = 16 * (C::WB > NOUTB_K ? C::WB : NOUTB_K);
+    static constexpr int RH = 16 * (C::WB > C::NINB ? C::WB : C::NINB);
+    static constexpr int PAD = DT == DT_F32 ? 4 : 8;
+    static constexpr int SD = kTrainPts + PAD;              // row stride (elements)
+    static constexpr int ELEM = DT == DT_F32 ? 4 : 2;
+    static constexpr size_t SMEM = (size_t)(RD + RH) * SD * ELEM;
+    static constexpr int KCMAX = kchunks<DT>(C::WB > C::NINB ? (C::WB > NOUTB_K ? C::WB : NOUTB_K)
+                                                             : (C::NINB > NOUTB_K ? C::NINB : NOUTB_K));
+};
+
+// Shapes whose weight-gradient accumulators fit the register budget (at most
+// 16 owned 16x16 tiles per wave) get a training kernel.
+template <class C> constexpr bool train_built() {
+    return TrainShape<C>::ACC <= 16 && TrainShape<C>::SMEM <= 96 * 1024;
+}
+
+// delta_{k-1} (or d_enc) = W^T delta, with W^T fragments (rows = input neurons, K = output neurons).
+template <int DT, int NBK, int NBI>
+__device__ inline void back_layer(const typename Mma<DT>::elem* WT, int lane, const float (&d)[kTrainSub][NBK][4],
+                                  float (&out)[kTrainSub][NBI][4]) {
+    using M = Mma<DT>;
+    constexpr int KC = kchunks<DT>(NBK);
+#pragma unroll
+    for (int ib = 0; ib < NBI; ++ib) {
+        float4_t acc[kTrainSub];
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const typename M::frag a = load_frag<DT>(WT, ib, kc, KC, lane);
+#pragma unroll
+            for (int s = 0; s < kTrainSub; ++s) acc[s] = M::mma(a, make_frag<DT, NBK>(d[s], kc), acc[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[s][ib][i] = acc[s][i];
+    }
+}
+
+template <int DT, int NBI, int NBO>
+__device__ inline void fwd_layer(const typename Mma<DT>::elem* W, int lane, const float (&in)[kTrainSub][NBI][4],
+                                 float (&out)[kTrainSub][NBO][4]) {
+    using M = Mma<DT>;
+    constexpr int KC = kchunks<DT>(NBI);
+#pragma unroll
+    for (int ob = 0; ob < NBO; ++ob) {
+        float4_t acc[kTrainSub];
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            const typename M::frag a = load_frag<DT>(W, ob, kc, KC, lane);
+#pragma unroll
+            for (int s = 0; s < kTrainSub; ++s) acc[s] = M::mma(a, make_frag<DT, NBI>(in[s], kc), acc[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[s][ob][i] = acc[s][i];
+    }
+}
+
+// Round a register activation array to the matrix-core dtype (what the MFMA
+// consumed), so staging and masks see the same values as the products.
+template <int DT, int NB>
+__device__ inline void round_to_dtype(float (&a)[kTrainSub][NB][4]) {
+#pragma unroll
+    for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[s][b][i] = (float)Mma<DT>::cvt(a[s][b][i]);
+}
+
+template <int DT, int NB>
+__device__ inline void stage(typename Mma<DT>::elem* buf, int SD, int wave, int lane, const float (&a)[kTrainSub][NB][4]) {
+    const int grp = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                buf[(16 * b + 4 * grp + i) * SD + wave * 32 + s * 16 + col] = Mma<DT>::cvt(a[s][b][i]);
+}
+
+// acc[j] += tile (ob, ib) of delta h^T over the block's samples, for the wave's owned tiles.
+template <int DT, int NBI, int NBO, int OWN, int OFF, int ACC, int SD>
+__device__ inline void accumulate_dw(const typename Mma<DT>::elem* D, const typename Mma<DT>::elem* H, int wave,
+                                     int lane, float4_t (&acc)[ACC]) {
+    using M = Mma<DT>;
+    using E = typename M::elem;
+    const int grp = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int j = 0; j < OWN; ++j) {
+        const int t = j * kTrainWaves + wave;
+        if (t >= NBI * NBO) break;
+        const int ob = t / NBI, ib = t % NBI;
+        const E* arow = D + (16 * ob + col) * SD;
+        const E* brow = H + (16 * ib + col) * SD;
+        float4_t c = acc[OFF + j];
+        if constexpr (DT == DT_F32) {
+#pragma unroll 8
+            for (int kc = 0; kc < kTrainPts / 4; ++kc) c = M::mma(arow[4 * kc + grp], brow[4 * kc + grp], c);
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < kTrainPts / 32; ++kc) {
+                const typename M::frag a = *reinterpret_cast<const typename M::frag*>(arow + 32 * kc + 8 * grp);
+                const typename M::frag b = *reinterpret_cast<const typename M::frag*>(brow + 32 * kc + 8 * grp);
+                c = M::mma(a, b, c);
+            }
+        }
+        acc[OFF + j] = c;
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
+    constexpr int DT = C::DT;
+    using M = Mma<DT>;
+    using E = typename M::elem;
+    using TS = TrainShape<C>;
+    constexpr int NL = TS::NL;
+    constexpr int SD = TS::SD;
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+    E* stD = reinterpret_cast<E*>(smem_raw);
+    E* stH = stD + TS::RD * SD;
+    __shared__ float red[kTrainWaves];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int grp = lane >> 4;
+    const int col = lane & 15;
+    const E* packed = reinterpret_cast<const E*>(a.packed);
+
+    float4_t acc[TS::ACC];
+#pragma unroll
+    for (int j = 0; j < TS::ACC; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    float loss_acc = 0.0f;
+
+    const int64_t iters = (a.batch + kTrainPts - 1) / kTrainPts;
+    for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        // ---------------- forward (recomputed) ----------------
+        float x[kTrainSub][3];
+        bool valid[kTrainSub];
+        float h0[kTrainSub][C::NINB][4];
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s) {
+            const int64_t b = it * kTrainPts + wave * 32 + s * 16 + col;
+            valid[s] = b < a.batch;
+            const int64_t bc = valid[s] ? b : a.batch - 1;
+            const int64_t src = a.pix ? (int64_t)a.pix[bc] : bc;
+            x[s][0] = clamp_unit(a.pos[src * 3 + 0]);
+            x[s][1] = clamp_unit(a.pos[src * 3 + 1]);
+            x[s][2] = clamp_unit(a.pos[src * 3 + 2]);
+            encode_lane<C::F, C::NINB>(a.table, a.g, grp, x[s][0], x[s][1], x[s][2], h0[s]);
+        }
+        round_to_dtype<DT, C::NINB>(h0);
+        float hh[C::NHID][kTrainSub][C::WB][4];        // inputs of layers 1..NHID (post-activation)
+        fwd_layer<DT, C::NINB, C::WB>(packed + a.off_f[0], lane, h0, hh[0]);
+        static_for<1, C::NHID + 1>([&](auto kc_) {
+            constexpr int k = decltype(kc_)::value;
+#pragma unroll
+            for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+                for (int b = 0; b < C::WB; ++b)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float v = hh[k - 1][s][b][i];
+                        hh[k - 1][s][b][i] = v > 0.0f ? v : (a.act ? a.slope * v : 0.0f);
+                    }
+            round_to_dtype<DT, C::WB>(hh[k - 1]);
+            if constexpr (k < C::NHID) fwd_layer<DT, C::WB, C::WB>(packed + a.off_f[k], lane, hh[k - 1], hh[k]);
+        });
+        float z[kTrainSub][TS::NOUTB_K][4];
+        {
+            float zz[kTrainSub][C::NOUTB][4];
+            fwd_layer<DT, C::WB, C::NOUTB>(packed + a.off_f[NL - 1], lane, hh[C::NHID - 1], zz);
+#pragma unroll
+            for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+                for (int b = 0; b < TS::NOUTB_K; ++b)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) z[s][b][i] = b < C::NOUTB ? zz[s][b][i] : 0.0f;
+        }
+
+        // ---------------- output gradient and loss ----------------
+        float d[kTrainSub][TS::NOUTB_K][4];
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s) {
+            const int64_t b = it * kTrainPts + wave * 32 + s * 16 + col;
+#pragma unroll
+            for (int ob = 0; ob < TS::NOUTB_K; ++ob)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int li = 16 * ob + 4 * grp + i;
+                    float g = 0.0f;
+                    if (valid[s] && li < a.n_out) {
+                        const float zv = z[s][ob][i];
+                        const float v = sigmoidf_(zv);
+                        if (a.labels) {
+                            const float y = (float)a.labels[b * a.n_out + li];
+                            if (a.loss == 0) {
+                                g = v - y;
+                                loss_acc += fmaxf(zv, 0.0f) + log1pf(expf(-fabsf(zv))) - y * zv;
+                            } else {
+                                g = 2.0f * (v - y) * v * (1.0f - v);
+                                loss_acc += (v - y) * (v - y);
+                            }
+                        } else {
+                            g = a.dvis[b * a.n_out + li] * v * (1.0f - v);
+                        }
+                        g *= a.out_mul;
+                    }
+                    d[s][ob][i] = g;
+                }
+        }
+
+        // ---------------- backward, output layer first ----------------
+        float dh[kTrainSub][C::WB][4];      // delta of the current hidden layer
+        float denc[kTrainSub][C::NINB][4];
+        static_for<0, NL>([&](auto kk_) {
+            constexpr int k = NL - 1 - decltype(kk_)::value;
+            // 1. stage delta_k and the layer input h_k
+            if constexpr (k == NL - 1) {
+                round_to_dtype<DT, TS::NOUTB_K>(d);
+                stage<DT, TS::NOUTB_K>(stD, SD, wave, lane, d);
+            } else {
+                round_to_dtype<DT, C::WB>(dh);
+                stage<DT, C::WB>(stD, SD, wave, lane, dh);
+            }
+            if constexpr (k == 0)
+                stage<DT, C::NINB>(stH, SD, wave, lane, h0);
+            else
+                stage<DT, C::WB>(stH, SD, wave, lane, hh[k - 1]);
+            // 2. propagate
+            if constexpr (k > 0) {
+                float nd[kTrainSub][C::WB][4];
+                if constexpr (k == NL - 1)
+                    back_layer<DT, TS::NOUTB_K, C::WB>(packed + a.off_b[k], lane, d, nd);
+                else
+                    back_layer<DT, C::WB, C::WB>(packed + a.off_b[k], lane, dh, nd);
+#pragma unroll
+                for (int s = 0; s < kTrainSub; ++s)
+#pragma unroll
+                    for (int b = 0; b < C::WB; ++b)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float h = hh[k - 1][s][b][i];
+                            dh[s][b][i] = nd[s][b][i] * (h > 0.0f ? 1.0f : (a.act ? a.slope : 0.0f));
+                        }
+            } else {
+                back_layer<DT, C::WB, C::NINB>(packed + a.off_b[0], lane, dh, denc);
+            }
+            __syncthreads();
+            // 3. weight-gradient tiles over the block's samples
+            accumulate_dw<DT, TS::nbi(k), TS::nbo(k), TS::owned(k), TS::acc_off(k), TS::ACC, SD>(stD, stH, wave,
+                                                                                                  lane, acc);
+            __syncthreads();
+        });
+
+        // ---------------- hash-table gradient ----------------
+#pragma unroll
+        for (int s = 0; s < kTrainSub; ++s) {
+            if (!valid[s]) continue;
+#pragma unroll
+            for (int b = 0; b < C::NINB; ++b) {
+#pragma unroll
+                for (int q = 0; q < 4; q += C::F) {
+                    const int feat = 16 * b + 4 * grp + q;
+                    const int l = feat / C::F;
+                    if (l >= a.g.n_levels) continue;
+                    Corners cr;
+                    level_corners(a.g, l, x[s][0], x[s][1], x[s][2], cr);
+                    float* gl = a.g_table + (size_t)l * a.g.T * C::F;
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                        for (int j = 0; j < C::F; ++j)
+                            unsafeAtomicAdd(gl + (size_t)cr.idx[kk] * C::F + j,
+                                            cr.w[kk] * (denc[s][b][q + j] * a.final_mul));
+                }
+            }
+        }
+    }
+
+    // ---------------- write the block's partial weight gradient and loss ----------------
+    float* part = a.ws_w + (int64_t)blockIdx.x * a.n_w;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int nbi = TS::nbi(k), nbo = TS::nbo(k);
+        const int in = a.lin[k], out = a.lout[k];
+        float* wk = part + a.w_off[k];
+#pragma unroll
+        for (int j = 0; j < TS::owned(k); ++j) {
+            const int t = j * kTrainWaves + wave;
+            if (t >= nbi * nbo) break;
+            const int ob = t / nbi, ib = t % nbi;
+            const float4_t c = acc[TS::acc_off(k) + j];
+            const int ci = 16 * ib + col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ro = 16 * ob + 4 * grp + i;
+                if (ro < out && ci < in) wk[(int64_t)ro * in + ci] = c[i] * a.final_mul;
+            }
+        }
+    }
+    // Tiles no wave owns do not exist, but entries of partially covered tiles
+    // outside (out, in) are skipped above; every (ro, ci) inside is written
+    // exactly once because each tile has one owner.
+    for (int off = 32; off > 0; off >>= 1) loss_acc += __shfl_xor(loss_acc, off);
+    if (lane == 0) red[wave] = loss_acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float sacc = 0.0f;
+        for (int w = 0; w < kTrainWaves; ++w) sacc += red[w];
+        a.ws_loss[blockIdx.x] = sacc;
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ ws_w,
+                                                             const float* __restrict__ ws_loss, int nblocks,
+                                                             int64_t n_w, float* __restrict__ g_w,
+                                                             float* __restrict__ loss_out, float loss_norm) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_w) {
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += ws_w[(int64_t)b * n_w + j];
+        g_w[j] += s;
+    } else if (j == n_w && loss_out) {
+        float s = 0.0f;
+        for (int b = 0; b < nblocks; ++b) s += ws_loss[b];
+        *loss_out = s * loss_norm;
+    }
+}
+
+static int train_grid(int64_t batch) {
+    const int64_t iters = (batch + kTrainPts - 1) / kTrainPts;
+    int64_t g = (int64_t)cu_count() * 2;
+    if (g > iters) g = iters;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+bool train_supported(const GridHost& g, const NetShape& s) {
+    bool ok = false;
+    dispatch_config(g.n_feat, s, [&]<class C>() { ok = train_built<C>(); });
+    return ok;
+}
+
+int64_t train_workspace_bytes(const GridHost&, const NetShape& s, int64_t batch) {
+    int64_t n_w = (int64_t)s.n_in * s.width + (int64_t)(s.n_hidden - 1) * s.width * s.width + (int64_t)s.width * s.n_out;
+    const int G = train_grid(batch);
+    return ((int64_t)G * n_w + G) * 4 + 256;
+}
+
+hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
+                        const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                        const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
+                        float* g_w, float* loss_out, void* workspace, hipStream_t st) {
+    TrainArgs a{};
+    a.g = grid_to_dev(gh);
+    a.table = table;
+    a.packed = packed;
+    a.n_w = 0;
+    for (int k = 0; k < plan.n_layers; ++k) {
+        a.off_f[k] = plan.layer[k].off_f;
+        a.off_b[k] = plan.layer[k].off_b;
+        a.w_off[k] = plan.layer[k].w_off;
+        a.lin[k] = plan.layer[k].in;
+        a.lout[k] = plan.layer[k].out;
+        a.n_w += (int64_t)plan.layer[k].in * plan.layer[k].out;
+    }
+    a.pos = pos;
+    a.pix = pix;
+    a.batch = batch;
+    a.n_out = s.n_out;
+    a.labels = labels;
+    a.dvis = dvis;
+    a.loss = loss;
+    const double count = (double)batch * s.n_out;
+    if (labels) {
+        const double gs = grad_scale > 0.0f ? grad_scale : count;
+        a.out_mul = (float)(gs / count);
+        a.final_mul = (float)(1.0 / gs);
+    } else {
+        const double gs = grad_scale > 0.0f ? grad_scale : 1.0;
+        a.out_mul = (float)gs;
+        a.final_mul = (float)(1.0 / gs);
+    }
+    a.g_table = g_table;
+    const int G = train_grid(batch);
+    a.ws_w = reinterpret_cast<float*>(workspace);
+    a.ws_loss = a.ws_w + (int64_t)G * a.n_w;
+    a.act = s.act;
+    a.slope = s.slope;
+    hipError_t err = hipErrorNotSupported;
+    dispatch_config(gh.n_feat, s, [&]<class C>() {
+        if constexpr (train_built<C>()) {
+            hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM, st, a);
+            err = hipGetLastError();
+        }
+    });
+    if (err != hipSuccess) return err;
+    const int64_t nthreads = a.n_w + 1;
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, a.ws_w,
+                       a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
+    return hipGetLastError();
+}
+
+}  // namespace nvc

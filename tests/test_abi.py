@@ -1,0 +1,140 @@
+"""The C ABI library loads, exports every entry point of include/nvc.h, and
+validates arguments on the host (no GPU needed: every call here returns
+before anything is launched)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2506_05930_amd import _lib
+from paper_2506_05930_amd._lib import NvcGrid, NvcMlp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nvc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nvc_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (nvc_[a-z0-9_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_version_and_status_strings(lib):
+    assert lib.nvc_version() == 1
+    for code in range(0, -7, -1):
+        assert _lib.status_string(code) != "unknown status"
+    assert _lib.status_string(-99) == "unknown status"
+
+
+def g(**kw):
+    d = dict(n_levels=16, n_feat=2, log2_T=19, base_res=16, growth=1.447)
+    d.update(kw)
+    return NvcGrid(d["n_levels"], d["n_feat"], d["log2_T"], d["base_res"], d["growth"])
+
+
+def m(**kw):
+    d = dict(n_in=32, width=64, n_hidden=3, n_out=32, act=0, slope=0.01, dtype=1)
+    d.update(kw)
+    return NvcMlp(d["n_in"], d["width"], d["n_hidden"], d["n_out"], d["act"], d["slope"], d["dtype"])
+
+
+def test_grid_levels_match_published_formula(lib):
+    res = (ctypes.c_int32 * 16)()
+    dense = (ctypes.c_int32 * 16)()
+    assert lib.nvc_grid_levels(ctypes.byref(g()), res, dense) == 0
+    from oracle import hashgrid
+    assert list(res) == hashgrid.level_resolutions(16, 1.447, 16)
+    assert [bool(x) for x in dense] == [hashgrid.level_is_dense(r, 1 << 19) for r in res]
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(n_levels=0), _lib.NVC_ERR_SHAPE), (dict(n_levels=33), _lib.NVC_ERR_SHAPE),
+    (dict(n_feat=3), _lib.NVC_ERR_UNSUPPORTED), (dict(log2_T=9), _lib.NVC_ERR_SHAPE),
+    (dict(log2_T=25), _lib.NVC_ERR_SHAPE), (dict(base_res=0), _lib.NVC_ERR_SHAPE),
+    (dict(growth=0.5), _lib.NVC_ERR_SHAPE), (dict(growth=float("nan")), _lib.NVC_ERR_SHAPE),
+])
+def test_grid_validation(lib, bad, code):
+    assert lib.nvc_grid_levels(ctypes.byref(g(**bad)), None, None) == code
+
+
+def test_param_counts(lib):
+    assert lib.nvc_mlp_param_count(ctypes.byref(m())) == 32 * 64 + 2 * 64 * 64 + 64 * 32
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(n_in=16, width=32, n_hidden=2, n_out=8, dtype=0))) == 1792
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(dtype=7))) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(n_out=129))) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_mlp_packed_bytes(ctypes.byref(m())) >= 2 * 2 * 12288
+
+
+def test_calls_reject_bad_arguments_before_launching(lib):
+    P = ctypes.c_void_p(16)             # never dereferenced: validation fails first
+    N = None
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())
+    assert lib.nvc_encode(None, P, P, 10, P, 0, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_encode(gg, P, P, -1, P, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_encode(gg, P, P, 10, P, 9, N) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_encode(gg, None, P, 10, P, 0, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_encode(gg, None, None, 0, None, 0, N) == 0           # n == 0 is a no-op
+    assert lib.nvc_infer(gg, ctypes.byref(m(n_in=30)), P, P, P, 10, P, 1, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_infer(gg, ctypes.byref(m(width=48)), P, P, P, 10, P, 1, N) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_infer(gg, mm, None, P, P, 10, P, 1, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_infer(gg, mm, None, None, None, 0, None, 1, N) == 0
+    assert lib.nvc_sample_wrs(P, 1, 10, 0, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 129, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_select_pixels(0, 0, 0, 10, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, 1 << 31, 10, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, 100, 10, None, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_shadow_labels(P, N, 10, P, 0, P, 1, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_shadow_labels(P, N, 10, P, 32, None, 4, P, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_shadow_labels(P, N, 10, P, 128, P, 4000, P, N) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_adam(P, P, P, P, 10, 0, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, 1e-2, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(None, P, P, P, 10, 1, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL
+
+
+def test_train_step_validation(lib):
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())
+    P = ctypes.c_void_p(16)
+    N = None
+    ws = lib.nvc_train_workspace_bytes(gg, mm, 1 << 18)
+    assert ws > 0
+    # neither or both of labels / dvis
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, N, N, 0, 0.0, P, P, N, P, ws, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, P, P, 0, 0.0, P, P, N, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, P, N, 5, 0.0, P, P, N, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, P, N, 0, -1.0, P, P, N, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 1 << 18, P, N, 0, 0.0, P, P, N, P, ws - 1, N) == \
+        _lib.NVC_ERR_WORKSPACE
+    assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, P, N, 0, 0.0, P, P, N, None, ws, N) == _lib.NVC_ERR_WORKSPACE
+    # the 128-wide network has no training kernel yet
+    wide = ctypes.byref(m(width=128, n_out=128))
+    g20 = ctypes.byref(g(log2_T=20))
+    assert lib.nvc_train_workspace_bytes(g20, wide, 1024) == _lib.NVC_ERR_UNSUPPORTED
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+
+    from paper_2506_05930_amd import api
+    grid = api.make_grid(8, 2, 14, 16, 1.5)
+    with pytest.raises(ValueError):
+        api.nvc_encode(grid, torch.zeros(8, 1 << 14, 2), torch.zeros(4, 3), torch.zeros(4, 16))
