@@ -1,0 +1,238 @@
+"""Benchmark of the cache's hot path on one MI355X: one step = one 1920x1080 frame with 32 lights.
+
+A step runs every stage of the path on synthetic data resident in HBM:
+  infer   hash-grid encoding + MLP for all 2,073,600 pixels   (nvc_infer, FP16 matrix cores)
+  wrs     weighted reservoir light pick + neural DI per pixel   (nvc_sample_wrs)
+  pixels  2^18 training pixels                                  (nvc_select_pixels)
+  labels  2^18 x 32 shadow rays against 256 spheres             (nvc_shadow_labels)
+  train   recomputed forward, backward, table scatter           (nvc_train_step)
+  adam    Adam on 16.8M table + 12,288 MLP params, repack        (nvc_adam x2, nvc_pack_mlp)
+
+Prints one JSON line.  `value` is visibility queries/s (one query = one pixel
+against all 32 lights) over whole frames, training included.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks.
+PEAK_HBM_GBS = 8000.0
+PEAK_F16_TFLOPS = 2500.0
+# Non-packed FP32 vector ALU: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 operations/s.
+PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+STAGES = ["infer", "wrs", "pixels", "labels", "train", "adam"]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="train_1080p")
+    ap.add_argument("--dtype", default=None, help="override the MLP dtype (f32, f16, bf16)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=262144, help="pixels of the oracle's timed sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=256,
+                    help="size of a plain device copy run after timing (counter calibration); 0 = none")
+    return ap.parse_args()
+
+
+def algorithmic(wl, n_pix, batch):
+    """Algorithmic bytes / operations of each stage for one frame (see the design notes)."""
+    L, F, M = wl.grid.n_levels, wl.grid.n_feat, wl.mlp.n_out
+    n_params = wl.grid.n_params + wl.mlp.n_params
+    vis_b = 2 if wl.mlp.dtype != "f32" else 4
+    return {
+        # 12 B position + 8 corners x F x 4 B per level + M visibilities out
+        "infer": {"bytes": n_pix * (12 + L * 8 * F * 4 + M * vis_b), "flops": n_pix * wl.mlp.flops_per_point},
+        # visibilities + position + normal in, index/pmf/W/DI out
+        "wrs": {"bytes": n_pix * (M * vis_b + 24 + 16)},
+        "pixels": {"bytes": batch * 4},
+        # segment-sphere tests, ~13 FP32 operations each
+        "labels": {"ops": batch * M * wl.n_spheres * 13, "bytes": batch * (12 + 4 + M)},
+        # forward + backward (3x the forward flops); 8 corners x F gathers and atomics per level
+        "train": {"flops": batch * 3 * wl.mlp.flops_per_point,
+                  "bytes": batch * (12 + 4 + M + 2 * L * 8 * F * 4)},
+        # read p, g, m, v; write p, m, v, g(=0)
+        "adam": {"bytes": n_params * 32},
+    }
+
+
+def cpu_baseline(wl, scene, params, sample_pix: int):
+    """The oracle, as it stands, on a bounded sample of the same frame, extrapolated to a frame."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hashgrid, lighting, philox, pipeline, shadow, training
+
+    n_pix = scene["pos"].shape[0]
+    sel = np.arange(sample_pix)
+    batch_s = max(1024, wl.train_batch // 4)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        vis = pipeline.infer(scene["pos_unit"][sel], params["table"], params["weights"], wl.grid.base_res,
+                             wl.grid.growth)
+        pipeline.sample(vis, scene["pos"][sel], scene["nrm"][sel], scene["lights"], wl.rng_key, 0, wl.vis_floor)
+        t1 = time.perf_counter()
+        pix = philox.training_pixels(wl.rng_key, 0, batch_s, n_pix)
+        y = shadow.labels_fp32(scene["pos"][pix], scene["lights"], scene["spheres"])
+        g = training.train_gradients(scene["pos_unit"][pix], params["table"], params["weights"], wl.grid.base_res,
+                                     wl.grid.growth, labels=y, loss=wl.loss)
+        t2 = time.perf_counter()
+        n_adam = 1 << 20
+        z = np.zeros(n_adam)
+        training.adam_step(params["table"].reshape(-1)[:n_adam], g["g_table"].reshape(-1)[:n_adam], z, z, 1,
+                           wl.lr, wl.beta1, wl.beta2, wl.adam_eps)
+        t3 = time.perf_counter()
+    frame_s = ((t1 - t0) * n_pix / sample_pix + (t2 - t1) * wl.train_batch / batch_s
+               + (t3 - t2) * (wl.grid.n_params + wl.mlp.n_params) / n_adam)
+    return {"value": n_pix / frame_s, "unit": "queries/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{sample_pix} pixels inference+WRS, {batch_s} training samples (labels+gradients), "
+                       f"Adam on {n_adam} params; FP64 NumPy, 1 thread, extrapolated linearly to one "
+                       f"{n_pix}-pixel frame with a {wl.train_batch}-sample step"),
+            "seconds": round(t3 - t0, 2), "ms_per_frame": frame_s * 1e3}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2506_05930_amd import api
+    from paper_2506_05930_amd.cache import NVCache
+    from workloads import box_scene, get_workload, init_params
+
+    over = {"mlp_dtype": args.dtype} if args.dtype else {}
+    wl = get_workload(args.workload, **over)
+    dev = torch.device("cuda:0")
+    scene = box_scene(wl.scene_seed, wl.width, wl.height, wl.n_boxes, wl.n_lights, wl.n_spheres)
+    params = init_params(wl.init_seed, wl.grid, wl.mlp)
+    n_pix = wl.width * wl.height
+    B = wl.train_batch
+    cache = NVCache(wl.grid, wl.mlp, params["table"], params["weights"], device=dev, seed=wl.rng_key, lr=wl.lr,
+                    beta1=wl.beta1, beta2=wl.beta2, eps=wl.adam_eps, loss=wl.loss, vis_floor=wl.vis_floor,
+                    max_batch=B)
+    pos_unit = torch.as_tensor(scene["pos_unit"]).to(dev)
+    pos = torch.as_tensor(scene["pos"]).to(dev)
+    nrm = torch.as_tensor(scene["nrm"]).to(dev)
+    lights = torch.as_tensor(scene["lights"]).to(dev)
+    spheres = torch.as_tensor(scene["spheres"]).to(dev)
+    vis = torch.empty((n_pix, wl.mlp.n_out), dtype=cache.vis_dtype, device=dev)
+    out = {k: torch.empty(n_pix, dtype=d, device=dev) for k, d in
+           (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
+    pix = torch.empty(B, dtype=torch.int32, device=dev)
+    labels = torch.empty((B, wl.mlp.n_out), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(frame, ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record(stream)
+        mark(0)
+        api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis)
+        mark(1)
+        api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
+                           out["wsum"], out["di"])
+        mark(2)
+        api.nvc_select_pixels(cache.seed, frame, n_pix, pix)
+        mark(3)
+        api.nvc_shadow_labels(pos, pix, lights, spheres, labels)
+        mark(4)
+        cache.gradients(pos_unit, labels=labels, pix=pix, batch=B)
+        mark(5)
+        cache.adam()
+        mark(6)
+
+    for f in range(args.warmup):
+        step(f)
+    torch.cuda.synchronize()
+
+    # Timed region: exactly `steps` frames between two synchronisations.
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for f in range(args.steps):
+        step(args.warmup + f)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = t_start.elapsed_time(t_end) / args.steps
+
+    # Per-stage durations from HIP events on the launch stream, over a second pass of `steps` frames.
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+    for f in range(args.steps):
+        step(args.warmup + args.steps + f, evs[f])
+    torch.cuda.synchronize()
+    stage_ms = {s: float(np.mean([evs[f][i].elapsed_time(evs[f][i + 1]) for f in range(args.steps)]))
+                for i, s in enumerate(STAGES)}
+    loss = float(cache.loss_buf.item())
+
+    if args.calibrate_copy_mib:
+        a = torch.empty(args.calibrate_copy_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    alg = algorithmic(wl, n_pix, B)
+    dominant = max(stage_ms, key=stage_ms.get)
+    rates = {}
+    for s, d in alg.items():
+        t = stage_ms[s] / 1e3
+        rates[s] = {k: v / t for k, v in d.items()}
+    if dominant == "labels":
+        roof = {"bound": "alu", "achieved": rates["labels"]["ops"] / 1e12, "peak": PEAK_ALU_TOPS,
+                "unit": "Tops/s"}
+    elif dominant in ("infer", "wrs", "adam", "train"):
+        roof = {"bound": "hbm", "achieved": rates[dominant]["bytes"] / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": rates[dominant]["bytes"] / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dominant
+    roof["traffic"] = None
+
+    q_infer_wrs = n_pix / ((stage_ms["infer"] + stage_ms["wrs"]) / 1e3)
+    result = {
+        "metric": "visibility queries/s (point x all lights) + ms/frame infer+train+WRS, 1080p x 32",
+        "value": n_pix / (ms_per_step / 1e3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.mlp.dtype,
+        "data": "synthetic",
+        "config": {"workload": wl.name, "pixels": n_pix, "lights": wl.n_lights, "spheres": wl.n_spheres,
+                   "train_batch": B, "grid": f"L{wl.grid.n_levels} F{wl.grid.n_feat} T2^{wl.grid.log2_T}",
+                   "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}"},
+        "ms_per_frame": ms_per_step,
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "queries_per_s_infer_wrs": q_infer_wrs,
+        "point_lights_per_s_infer_wrs": q_infer_wrs * wl.n_lights,
+        "stage_rates": {s: {k: round(v / 1e9, 2) for k, v in r.items()} for s, r in rates.items()},
+        "loss": loss,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(wl, scene, params, args.cpu_sample)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -238,6 +238,23 @@ __device__ inline void encode_lane(const float* __restrict__ table, const GridDe
     }
 }
 
+// Correctly rounded FP32 square root of a positive normal x.  The hardware
+// square root is accurate to 1 ulp but not correctly rounded; with s its
+// result and s-, s+ the neighbouring floats, the exact root lies below the
+// midpoint of (s-, s) iff x <= s- * s, and above the midpoint of (s, s+) iff
+// x > s * s+ (no float lies between those products and the squared
+// midpoints), and one fused multiply-add gives each sign exactly.
+__device__ inline float sqrt_rn(float x) {
+    float s = __builtin_amdgcn_sqrtf(x);
+    const float s_dn = __int_as_float(__float_as_int(s) - 1);
+    const float s_up = __int_as_float(__float_as_int(s) + 1);
+    if (fmaf(-s_dn, s, x) <= 0.0f)
+        s = s_dn;
+    else if (fmaf(-s_up, s, x) > 0.0f)
+        s = s_up;
+    return s;
+}
+
 // Logistic function evaluated from the FP32 accumulator.
 __device__ inline float sigmoidf_(float z) {
     if (z >= 0.0f) return 1.0f / (1.0f + expf(-z));

@@ -5,7 +5,8 @@
 // These kernels take integer decisions from FP32 arithmetic (the picked
 // light, the binary label), so every product and sum is a separately rounded
 // FP32 operation in the order documented in nvc.h: the library is built with
-// FP contraction off, and division and square root are correctly rounded.
+// FP contraction off, division is the compiler's correctly rounded sequence and
+// the square root is refined to the correctly rounded one (sqrt_rn).
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, in
             float f;
             if (has_n) {
                 const float nd = (nx * dx + ny * dy) + nz * dz;
-                f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * __fsqrt_rn(d2));
+                f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
             } else {
                 f = __fdiv_rn(l.w, d2);
             }
