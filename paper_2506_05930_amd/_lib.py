@@ -77,6 +77,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loading torch first makes libnvc.so bind to that runtime, so the streams
+    # and device pointers torch hands over belong to the runtime that launches
+    # the kernels.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or "
                            "python paper_2506_05930_amd/build.py first")

@@ -1,0 +1,195 @@
+// Routed scatter of the hash-table gradient: counting, offsets and the
+// per-partition LDS sums (see route.hpp).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "route.hpp"
+
+namespace nvc {
+
+GridDev grid_to_dev(const GridHost& g);
+
+RoutePlan make_route_plan(const GridHost& g) {
+    RoutePlan p{};
+    const uint64_t T = 1ull << g.log2_T;
+    for (int k = 12; k <= 14; ++k) {
+        const uint64_t ps = 1ull << k;
+        if (ps * (uint64_t)g.n_feat * 4 > 128 * 1024) break;
+        bool ok = true;
+        int nb = 0;
+        for (int l = 0; l < g.n_levels && ok; ++l) {
+            const bool dense = (g.dense_mask >> l) & 1u;
+            const uint64_t n1 = (uint64_t)g.res[l] + 1;
+            const uint64_t e = dense ? n1 * n1 * n1 : T;
+            // x-pairs of a hashed level must share a partition: cx + 1 < 2^k (or one partition only)
+            if (!dense && T > ps && (uint64_t)g.res[l] >= ps) ok = false;
+            p.bucket_off[l] = nb;
+            p.entries[l] = (uint32_t)e;
+            nb += (int)((e + ps - 1) / ps);
+        }
+        if (ok && nb <= kRouteMaxBuckets) {
+            p.ok = true;
+            p.k = k;
+            p.nb = nb;
+            p.bucket_off[g.n_levels] = nb;
+            return p;
+        }
+    }
+    p.ok = false;
+    return p;
+}
+
+// Counts the records each training block will emit, per bucket.  Block j owns
+// the same samples as training block j: b = it * P + t for it = j, j + G, ...
+template <int F>
+__global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r, const float* __restrict__ pos,
+                                                         const int32_t* __restrict__ pix, int64_t batch, int P) {
+    extern __shared__ uint32_t hist[];
+    for (int i = threadIdx.x; i < r.nb; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const int64_t iters = (batch + P - 1) / P;
+    const uint32_t M = (1u << r.k) - 1u;
+    const int lanes_per_level_set = 2;                       // thread halves split the levels
+    const int t = threadIdx.x % (blockDim.x / lanes_per_level_set);
+    const int half = threadIdx.x / (blockDim.x / lanes_per_level_set);
+    for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        for (int s = t; s < P; s += blockDim.x / lanes_per_level_set) {
+            const int64_t b = it * P + s;
+            if (b >= batch) continue;
+            const int64_t src = pix ? (int64_t)pix[b] : b;
+            const float x = clamp_unit(pos[src * 3 + 0]);
+            const float y = clamp_unit(pos[src * 3 + 1]);
+            const float z = clamp_unit(pos[src * 3 + 2]);
+            for (int l = half; l < g.n_levels; l += lanes_per_level_set) {
+                Corners cr;
+                level_corners(g, l, x, y, z, cr);
+                const bool dense = (g.dense_mask >> l) & 1u;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const uint32_t e0 = cr.idx[2 * p];
+                    if (dense && (e0 & M) == M) continue;          // straddler: direct atomics
+                    atomicAdd(&hist[r.bucket_off[l] + (e0 >> r.k)], 1u);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < r.nb; i += blockDim.x) r.offsets[(int64_t)blockIdx.x * r.nb + i] = hist[i];
+}
+
+// Per bucket: exclusive prefix over the blocks' counts (in place) and the total.
+__global__ __launch_bounds__(256) void route_prefix_kernel(RouteDev r, int G) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= r.nb) return;
+    uint32_t run = 0;
+    for (int j = 0; j < G; ++j) {
+        const uint32_t c = r.offsets[(int64_t)j * r.nb + b];
+        r.offsets[(int64_t)j * r.nb + b] = run;
+        run += c;
+    }
+    r.totals[b] = run;
+}
+
+// Exclusive prefix of the bucket totals; base[nb] = number of records.
+__global__ __launch_bounds__(1024) void route_scan_kernel(RouteDev r) {
+    __shared__ uint32_t part[1024];
+    constexpr int PER = kRouteMaxBuckets / 1024;
+    const int t = threadIdx.x;
+    uint32_t v[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = t * PER + i;
+        v[i] = b < r.nb ? r.totals[b] : 0u;
+        sum += v[i];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {               // inclusive Hillis-Steele scan
+        const uint32_t add = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;                             // exclusive
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = t * PER + i;
+        if (b < r.nb) r.base[b] = run;
+        run += v[i];
+    }
+    if (t == 1023) r.base[r.nb] = part[1023];
+}
+
+// One block per bucket: sum the bucket's records into an LDS copy of the
+// partition, then add the partition to the gradient.
+template <int F>
+__global__ __launch_bounds__(256) void route_accumulate_kernel(RouteDev r, int n_levels, uint32_t T,
+                                                              float* __restrict__ g_table) {
+    extern __shared__ float part[];
+    const int b = blockIdx.x;
+    int l = 0;
+    while (l + 1 < n_levels && r.bucket_off[l + 1] <= b) ++l;
+    const uint32_t ps = 1u << r.k;
+    const uint32_t pbase = (uint32_t)(b - r.bucket_off[l]) << r.k;
+    const uint32_t cnt = min(ps, r.entries[l] - pbase);
+    for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0.0f;
+    __syncthreads();
+    const uint32_t r0 = r.base[b], r1 = r.base[b + 1];
+    for (uint32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const uint32_t key = r.keys[i];
+        const uint32_t lo0 = key & 0xFFFFu, lo1 = key >> 16;
+        const float* v = r.vals + (size_t)i * (2 * F);
+        float w[2 * F];
+        if constexpr (F == 2) {
+            const float4 q = *reinterpret_cast<const float4*>(v);
+            w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 2 * F; ++j) w[j] = v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            atomicAdd(&part[lo0 * F + j], w[j]);
+            atomicAdd(&part[lo1 * F + j], w[F + j]);
+        }
+    }
+    __syncthreads();
+    float* out = g_table + ((size_t)l * T + pbase) * F;
+    for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x) out[i] += part[i];
+}
+
+hipError_t launch_route_count(const GridHost& gh, const RouteDev& r, const float* pos, const int32_t* pix,
+                              int64_t batch, int grid, int pts_per_iter, hipStream_t st) {
+    const GridDev g = grid_to_dev(gh);
+    const size_t smem = (size_t)r.nb * 4;
+    if (gh.n_feat == 1)
+        hipLaunchKernelGGL(route_count_kernel<1>, dim3(grid), dim3(256), smem, st, g, r, pos, pix, batch, pts_per_iter);
+    else if (gh.n_feat == 2)
+        hipLaunchKernelGGL(route_count_kernel<2>, dim3(grid), dim3(256), smem, st, g, r, pos, pix, batch, pts_per_iter);
+    else
+        hipLaunchKernelGGL(route_count_kernel<4>, dim3(grid), dim3(256), smem, st, g, r, pos, pix, batch, pts_per_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_route_prefix(const RouteDev& r, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(route_prefix_kernel, dim3((r.nb + 255) / 256), dim3(256), 0, st, r, grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(route_scan_kernel, dim3(1), dim3(1024), 0, st, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_route_accumulate(const GridHost& gh, const RouteDev& r, float* g_table, hipStream_t st) {
+    const uint32_t T = 1u << gh.log2_T;
+    const size_t smem = ((size_t)1 << r.k) * gh.n_feat * 4;
+    if (gh.n_feat == 1)
+        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+    else if (gh.n_feat == 2)
+        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+    else
+        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+    return hipGetLastError();
+}
+
+}  // namespace nvc

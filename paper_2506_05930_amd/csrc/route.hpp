@@ -1,0 +1,66 @@
+// Routed scatter of the hash-table gradient.
+//
+// Global FP32 atomics on gfx950 are limited by the number of distinct cache
+// lines per instruction, and the table gradient receives ~64 random updates
+// per training sample (2^18 samples x 16 levels x 8 corners x 2 features), so
+// scattering it with per-lane atomics is slow.  Instead every update is routed
+// to the 4096-entry (2^k) partition of the table it falls in and summed there
+// in LDS by the block that owns the partition:
+//
+//   count     for the samples each training block will own, count the records
+//             per partition ("bucket")                        route_count_kernel
+//   prefix    per bucket, an exclusive prefix over the blocks' counts gives
+//             every block a private write range              route_prefix_kernel
+//   scan      exclusive prefix of the bucket totals           route_scan_kernel
+//   emit      the training kernel writes one record per corner x-pair
+//             (the corners at dx = 0 and dx = 1 of one (dy, dz)) into its range
+//   sum       one block per partition sums its records in LDS and adds the
+//             partition to the gradient with plain, coalesced stores
+//                                                             route_accumulate_kernel
+//
+// A record carries both entries of an x-pair.  On a hashed level the low 12
+// (k) bits of the hash are the only ones the x coordinate reaches when
+// N < 2^k, so both entries always share a partition.  On a dense level the
+// pair (e, e+1) straddles a partition boundary when e is the partition's last
+// entry; those pairs (1 in 2^k) are added with direct atomics by the training
+// kernel, which runs before the partition sums.
+#pragma once
+
+#include <stdint.h>
+
+#include "nvc_internal.hpp"
+
+namespace nvc {
+
+constexpr int kRouteMaxBuckets = 8192;
+
+struct RouteDev {
+    int32_t enabled;
+    int32_t k;                                // partition = 2^k entries
+    int32_t nb;                               // buckets over all levels
+    int32_t bucket_off[kMaxLevels + 1];       // first bucket of each level
+    uint32_t entries[kMaxLevels];             // entries a level uses: (N+1)^3 dense, T hashed
+    uint32_t* offsets;                        // [G][nb]: counts, then each block's offset within the bucket
+    uint32_t* totals;                         // [nb]
+    uint32_t* base;                           // [nb + 1]: first record of each bucket
+    float* vals;                              // [R][2F]: values of entry e0, then of e1
+    uint32_t* keys;                           // [R]: (e0 & M) | (e1 & M) << 16, M = 2^k - 1
+};
+
+// Host-side plan: partition size, bucket numbering, whether routing applies.
+struct RoutePlan {
+    bool ok;
+    int k;
+    int nb;
+    int bucket_off[kMaxLevels + 1];
+    uint32_t entries[kMaxLevels];
+};
+
+RoutePlan make_route_plan(const GridHost& g);
+
+hipError_t launch_route_count(const GridHost& g, const RouteDev& r, const float* pos, const int32_t* pix,
+                              int64_t batch, int grid, int pts_per_iter, hipStream_t st);
+hipError_t launch_route_prefix(const RouteDev& r, int grid, hipStream_t st);
+hipError_t launch_route_accumulate(const GridHost& g, const RouteDev& r, float* g_table, hipStream_t st);
+
+}  // namespace nvc

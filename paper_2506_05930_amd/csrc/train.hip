@@ -23,6 +23,7 @@
 
 #include "device_common.hpp"
 #include "kernel_config.hpp"
+#include "route.hpp"
 
 namespace nvc {
 
@@ -64,6 +65,7 @@ struct TrainArgs {
     int64_t n_w;
     int act;
     float slope;
+    RouteDev route;       // routed table scatter (route.enabled == 0: direct atomics)
 };
 
 template <class C>
@@ -219,6 +221,14 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     const int col = lane & 15;
     const E* packed = reinterpret_cast<const E*>(a.packed);
 
+    // Write cursors of the routed scatter: this block's range in every bucket.
+    uint32_t* cursor = reinterpret_cast<uint32_t*>(smem_raw + TS::SMEM);
+    if (a.route.enabled) {
+        for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x)
+            cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)blockIdx.x * a.route.nb + i];
+        __syncthreads();
+    }
+
     float4_t acc[TS::ACC];
 #pragma unroll
     for (int j = 0; j < TS::ACC; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
@@ -359,12 +369,46 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
                     Corners cr;
                     level_corners(a.g, l, x[s][0], x[s][1], x[s][2], cr);
                     float* gl = a.g_table + (size_t)l * a.g.T * C::F;
+                    float dj[C::F];
 #pragma unroll
-                    for (int kk = 0; kk < 8; ++kk)
+                    for (int j = 0; j < C::F; ++j) dj[j] = denc[s][b][q + j] * a.final_mul;
+                    if (a.route.enabled) {
+                        const uint32_t M = (1u << a.route.k) - 1u;
+                        const bool dense = (a.g.dense_mask >> l) & 1u;
 #pragma unroll
-                        for (int j = 0; j < C::F; ++j)
-                            unsafeAtomicAdd(gl + (size_t)cr.idx[kk] * C::F + j,
-                                            cr.w[kk] * (denc[s][b][q + j] * a.final_mul));
+                        for (int p = 0; p < 4; ++p) {
+                            const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
+                            float v[2 * C::F];
+#pragma unroll
+                            for (int j = 0; j < C::F; ++j) {
+                                v[j] = cr.w[2 * p] * dj[j];
+                                v[C::F + j] = cr.w[2 * p + 1] * dj[j];
+                            }
+                            if (dense && (e0 & M) == M) {          // pair straddles two partitions
+#pragma unroll
+                                for (int j = 0; j < C::F; ++j) {
+                                    unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
+                                    unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
+                                }
+                                continue;
+                            }
+                            const uint32_t slot = atomicAdd(&cursor[a.route.bucket_off[l] + (e0 >> a.route.k)], 1u);
+                            float* dst = a.route.vals + (size_t)slot * (2 * C::F);
+                            if constexpr (C::F == 2) {
+                                *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                            } else {
+#pragma unroll
+                                for (int j = 0; j < 2 * C::F; ++j) dst[j] = v[j];
+                            }
+                            a.route.keys[slot] = (e0 & M) | ((e1 & M) << 16);
+                        }
+                    } else {
+#pragma unroll
+                        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                            for (int j = 0; j < C::F; ++j)
+                                unsafeAtomicAdd(gl + (size_t)cr.idx[kk] * C::F + j, cr.w[kk] * dj[j]);
+                    }
                 }
             }
         }
@@ -404,16 +448,21 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     }
 }
 
+// Sum of the blocks' partial weight gradients: slice y of the grid sums
+// blocks [y*G/S, (y+1)*G/S) and adds its sum to g_w (the weight gradient's
+// summation order across slices is not fixed).  The loss is summed once.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ ws_w,
                                                              const float* __restrict__ ws_loss, int nblocks,
                                                              int64_t n_w, float* __restrict__ g_w,
                                                              float* __restrict__ loss_out, float loss_norm) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int S = gridDim.y, y = blockIdx.y;
+    const int b0 = (int)((int64_t)nblocks * y / S), b1 = (int)((int64_t)nblocks * (y + 1) / S);
     if (j < n_w) {
         float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += ws_w[(int64_t)b * n_w + j];
-        g_w[j] += s;
-    } else if (j == n_w && loss_out) {
+        for (int b = b0; b < b1; ++b) s += ws_w[(int64_t)b * n_w + j];
+        unsafeAtomicAdd(g_w + j, s);
+    } else if (j == n_w && y == 0 && loss_out) {
         float s = 0.0f;
         for (int b = 0; b < nblocks; ++b) s += ws_loss[b];
         *loss_out = s * loss_norm;
@@ -434,10 +483,46 @@ bool train_supported(const GridHost& g, const NetShape& s) {
     return ok;
 }
 
-int64_t train_workspace_bytes(const GridHost&, const NetShape& s, int64_t batch) {
-    int64_t n_w = (int64_t)s.n_in * s.width + (int64_t)(s.n_hidden - 1) * s.width * s.width + (int64_t)s.width * s.n_out;
-    const int G = train_grid(batch);
-    return ((int64_t)G * n_w + G) * 4 + 256;
+// Workspace layout (each part 256-byte aligned):
+//   [G][n_w] partial weight gradients | [G] partial losses |
+//   routed scatter: [G][nb] offsets | [nb] totals | [nb+1] bases | [R][2F] values | [R] keys
+// with R = batch * n_levels * 4 records (one per corner x-pair).
+struct WsLayout {
+    int64_t w, loss, offsets, totals, base, vals, keys, total;
+};
+
+static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+static WsLayout ws_layout(const GridHost& g, int64_t n_w, int64_t batch, int G, const RoutePlan& rp) {
+    WsLayout L{};
+    int64_t o = 0;
+    L.w = o;
+    o = align256(o + (int64_t)G * n_w * 4);
+    L.loss = o;
+    o = align256(o + (int64_t)G * 4);
+    if (rp.ok) {
+        const int64_t R = batch * g.n_levels * 4;
+        L.offsets = o;
+        o = align256(o + (int64_t)G * rp.nb * 4);
+        L.totals = o;
+        o = align256(o + (int64_t)rp.nb * 4);
+        L.base = o;
+        o = align256(o + (int64_t)(rp.nb + 1) * 4);
+        L.vals = o;
+        o = align256(o + R * 2 * g.n_feat * 4);
+        L.keys = o;
+        o = align256(o + R * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+static int64_t n_weights(const NetShape& s) {
+    return (int64_t)s.n_in * s.width + (int64_t)(s.n_hidden - 1) * s.width * s.width + (int64_t)s.width * s.n_out;
+}
+
+int64_t train_workspace_bytes(const GridHost& g, const NetShape& s, int64_t batch) {
+    return ws_layout(g, n_weights(s), batch, train_grid(batch), make_route_plan(g)).total;
 }
 
 hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
@@ -476,21 +561,48 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     }
     a.g_table = g_table;
     const int G = train_grid(batch);
-    a.ws_w = reinterpret_cast<float*>(workspace);
-    a.ws_loss = a.ws_w + (int64_t)G * a.n_w;
+    const RoutePlan rp = make_route_plan(gh);
+    const WsLayout wl = ws_layout(gh, a.n_w, batch, G, rp);
+    unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+    a.ws_w = reinterpret_cast<float*>(ws + wl.w);
+    a.ws_loss = reinterpret_cast<float*>(ws + wl.loss);
     a.act = s.act;
     a.slope = s.slope;
-    hipError_t err = hipErrorNotSupported;
+    a.route = RouteDev{};
+    hipError_t err = hipSuccess;
+    if (rp.ok) {
+        RouteDev& r = a.route;
+        r.enabled = 1;
+        r.k = rp.k;
+        r.nb = rp.nb;
+        for (int l = 0; l <= kMaxLevels; ++l) r.bucket_off[l] = l <= gh.n_levels ? rp.bucket_off[l] : rp.nb;
+        for (int l = 0; l < kMaxLevels; ++l) r.entries[l] = rp.entries[l];
+        r.offsets = reinterpret_cast<uint32_t*>(ws + wl.offsets);
+        r.totals = reinterpret_cast<uint32_t*>(ws + wl.totals);
+        r.base = reinterpret_cast<uint32_t*>(ws + wl.base);
+        r.vals = reinterpret_cast<float*>(ws + wl.vals);
+        r.keys = reinterpret_cast<uint32_t*>(ws + wl.keys);
+        err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
+        if (err == hipSuccess) err = launch_route_prefix(r, G, st);
+        if (err != hipSuccess) return err;
+    }
+    err = hipErrorNotSupported;
+    const size_t cursor_bytes = rp.ok ? (size_t)rp.nb * 4 : 0;
     dispatch_config(gh.n_feat, s, [&]<class C>() {
         if constexpr (train_built<C>()) {
-            hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM, st, a);
+            hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM + cursor_bytes, st, a);
             err = hipGetLastError();
         }
     });
     if (err != hipSuccess) return err;
+    if (a.route.enabled) {
+        err = launch_route_accumulate(gh, a.route, g_table, st);
+        if (err != hipSuccess) return err;
+    }
     const int64_t nthreads = a.n_w + 1;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, a.ws_w,
-                       a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
+    const int slices = std::min(G, 16);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nthreads + 255) / 256), slices), dim3(256), 0, st,
+                       a.ws_w, a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
     return hipGetLastError();
 }
 

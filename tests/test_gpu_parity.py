@@ -307,3 +307,49 @@ def test_adam_matches_oracle():
     assert np.abs(M.cpu().numpy() - rm).max() <= 1e-7
     assert np.abs(V.cpu().numpy() - rv).max() <= 1e-9
     assert G.abs().max().item() == 0.0
+
+
+def _straddling_points():
+    """Vertices-centred points whose (dy, dz) = (0, 0) corner pair straddles a 4096-entry partition
+    on the dense level of resolution 48 (1080p grid, level 3): e0 = cx + 49 cy + 49^2 cz = 4095 (mod 4096)."""
+    pts = []
+    for cz in range(0, 20):
+        for cy in range(0, 48):
+            cx = (4095 + 4096 * 8 - 49 * cy - 2401 * cz) % 4096
+            if cx < 48 and (cx + 49 * cy + 2401 * cz) % 4096 == 4095:
+                pts.append([(cx + 0.5) / 48, (cy + 0.5) / 48, (cz + 0.5) / 48])
+    return np.array(pts, np.float32)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 3e-2)])
+def test_train_routed_scatter_edge_cases(dtype, tol):
+    wl = p1080()
+    p = params(wl)
+    cache = make_cache(wl, p, dtype=dtype)
+    strad = _straddling_points()
+    assert len(strad) >= 5
+    same = np.tile(np.array([[0.3, 0.6, 0.2]], np.float32), (300, 1))     # one cell: heavy bucket
+    pos = np.concatenate([strad, same, rand_pos(31, 777)]).astype(np.float32)  # ragged batch
+    y = (np.random.default_rng(32).uniform(size=(len(pos), 32)) > 0.5).astype(np.uint8)
+    cache.gradients(t(pos), labels=t(y))
+    ref = training.train_gradients(pos, p["table"], p["weights"], 16, 1.447, labels=y)
+    assert _rel_l2(cache.g_table.cpu().numpy(), ref["g_table"]) <= tol
+    ref_w = np.concatenate([g.ravel() for g in ref["g_w"]])
+    assert _rel_l2(cache.g_w.cpu().numpy(), ref_w) <= tol
+
+
+def test_train_direct_atomic_fallback_for_fine_hashed_levels():
+    """Growth 2.0 gives hashed levels finer than 2^14 cells per axis, which the routed scatter
+    does not partition; the training step falls back to direct atomics and stays exact."""
+    from dataclasses import replace
+
+    from paper_2506_05930_amd.cache import NVCache
+    wl = p1080()
+    grid = replace(wl.grid, growth=2.0)
+    p = params(wl)
+    cache = NVCache(grid, replace(wl.mlp, dtype="f32"), p["table"], p["weights"], device=DEV)
+    pos = rand_pos(33, 1000)
+    y = (np.random.default_rng(34).uniform(size=(1000, 32)) > 0.5).astype(np.uint8)
+    cache.gradients(t(pos), labels=t(y))
+    ref = training.train_gradients(pos, p["table"], p["weights"], 16, 2.0, labels=y)
+    assert _rel_l2(cache.g_table.cpu().numpy(), ref["g_table"]) <= 1e-4
