@@ -74,20 +74,32 @@ __global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r,
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < r.nb; i += blockDim.x) r.offsets[(int64_t)blockIdx.x * r.nb + i] = hist[i];
+    for (int i = threadIdx.x; i < r.nb; i += blockDim.x) r.offsets[(int64_t)i * gridDim.x + blockIdx.x] = hist[i];
 }
 
-// Per bucket: exclusive prefix over the blocks' counts (in place) and the total.
+// Per bucket (one wave each): exclusive prefix over the blocks' counts, in place,
+// and the bucket total.
 __global__ __launch_bounds__(256) void route_prefix_kernel(RouteDev r, int G) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= r.nb) return;
-    uint32_t run = 0;
-    for (int j = 0; j < G; ++j) {
-        const uint32_t c = r.offsets[(int64_t)j * r.nb + b];
-        r.offsets[(int64_t)j * r.nb + b] = run;
+    uint32_t* row = r.offsets + (int64_t)b * G;
+    const int per = (G + 63) / 64;
+    const int j0 = lane * per;
+    uint32_t sum = 0;
+    for (int j = j0; j < j0 + per && j < G; ++j) sum += row[j];
+    uint32_t incl = sum;                                       // inclusive wave scan of the lane sums
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    uint32_t run = incl - sum;
+    for (int j = j0; j < j0 + per && j < G; ++j) {
+        const uint32_t c = row[j];
+        row[j] = run;
         run += c;
     }
-    r.totals[b] = run;
+    if (lane == 63) r.totals[b] = incl;
 }
 
 // Exclusive prefix of the bucket totals; base[nb] = number of records.
@@ -95,55 +107,79 @@ __global__ __launch_bounds__(1024) void route_scan_kernel(RouteDev r) {
     __shared__ uint32_t part[1024];
     constexpr int PER = kRouteMaxBuckets / 1024;
     const int t = threadIdx.x;
-    uint32_t v[PER];
-    uint32_t sum = 0;
+    __shared__ uint32_t cpart[1024];
+    uint32_t v[PER], c[PER];
+    uint32_t sum = 0, csum = 0;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = t * PER + i;
         v[i] = b < r.nb ? r.totals[b] : 0u;
+        c[i] = (v[i] + kRouteChunk - 1) / kRouteChunk;
         sum += v[i];
+        csum += c[i];
     }
     part[t] = sum;
+    cpart[t] = csum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {               // inclusive Hillis-Steele scan
+    for (int off = 1; off < 1024; off <<= 1) {               // inclusive Hillis-Steele scans
         const uint32_t add = t >= off ? part[t - off] : 0u;
+        const uint32_t cadd = t >= off ? cpart[t - off] : 0u;
         __syncthreads();
         part[t] += add;
+        cpart[t] += cadd;
         __syncthreads();
     }
-    uint32_t run = part[t] - sum;                             // exclusive
+    uint32_t run = part[t] - sum, crun = cpart[t] - csum;     // exclusive
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int b = t * PER + i;
-        if (b < r.nb) r.base[b] = run;
+        if (b < r.nb) {
+            r.base[b] = run;
+            r.chunk_base[b] = crun;
+        }
         run += v[i];
+        crun += c[i];
     }
-    if (t == 1023) r.base[r.nb] = part[1023];
+    if (t == 1023) {
+        r.base[r.nb] = part[1023];
+        r.chunk_base[r.nb] = cpart[1023];
+    }
 }
 
-// One block per bucket: sum the bucket's records into an LDS copy of the
-// partition, then add the partition to the gradient.
+// One block per chunk of a bucket: sum the chunk's records into an LDS copy of
+// the partition, then add it to the gradient (plain stores if the bucket has a
+// single chunk, atomics otherwise; 16 lanes cover one 64-byte line).
 template <int F>
 __global__ __launch_bounds__(256) void route_accumulate_kernel(RouteDev r, int n_levels, uint32_t T,
                                                               float* __restrict__ g_table) {
     extern __shared__ float part[];
-    const int b = blockIdx.x;
+    const uint32_t c = blockIdx.x;
+    if (c >= r.chunk_base[r.nb]) return;
+    int lo = 0, hi = r.nb;                                   // bucket b: chunk_base[b] <= c < chunk_base[b+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (r.chunk_base[mid] <= c) lo = mid; else hi = mid;
+    }
+    const int b = lo;
     int l = 0;
     while (l + 1 < n_levels && r.bucket_off[l + 1] <= b) ++l;
     const uint32_t ps = 1u << r.k;
     const uint32_t pbase = (uint32_t)(b - r.bucket_off[l]) << r.k;
     const uint32_t cnt = min(ps, r.entries[l] - pbase);
+    const uint32_t q = c - r.chunk_base[b];
+    const bool shared = r.chunk_base[b + 1] - r.chunk_base[b] > 1;
+    const uint32_t r0 = r.base[b] + q * (uint32_t)kRouteChunk;
+    const uint32_t r1 = min(r.base[b + 1], r0 + (uint32_t)kRouteChunk);
     for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0.0f;
     __syncthreads();
-    const uint32_t r0 = r.base[b], r1 = r.base[b + 1];
     for (uint32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
         const uint32_t key = r.keys[i];
         const uint32_t lo0 = key & 0xFFFFu, lo1 = key >> 16;
         const float* v = r.vals + (size_t)i * (2 * F);
         float w[2 * F];
         if constexpr (F == 2) {
-            const float4 q = *reinterpret_cast<const float4*>(v);
-            w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
+            const float4 qv = *reinterpret_cast<const float4*>(v);
+            w[0] = qv.x; w[1] = qv.y; w[2] = qv.z; w[3] = qv.w;
         } else {
 #pragma unroll
             for (int j = 0; j < 2 * F; ++j) w[j] = v[j];
@@ -156,7 +192,12 @@ __global__ __launch_bounds__(256) void route_accumulate_kernel(RouteDev r, int n
     }
     __syncthreads();
     float* out = g_table + ((size_t)l * T + pbase) * F;
-    for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x) out[i] += part[i];
+    if (shared) {
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x)
+            if (part[i] != 0.0f) unsafeAtomicAdd(out + i, part[i]);
+    } else {
+        for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x) out[i] += part[i];
+    }
 }
 
 hipError_t launch_route_count(const GridHost& gh, const RouteDev& r, const float* pos, const int32_t* pix,
@@ -173,22 +214,26 @@ hipError_t launch_route_count(const GridHost& gh, const RouteDev& r, const float
 }
 
 hipError_t launch_route_prefix(const RouteDev& r, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(route_prefix_kernel, dim3((r.nb + 255) / 256), dim3(256), 0, st, r, grid);
+    hipLaunchKernelGGL(route_prefix_kernel, dim3((r.nb + 3) / 4), dim3(256), 0, st, r, grid);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(route_scan_kernel, dim3(1), dim3(1024), 0, st, r);
     return hipGetLastError();
 }
 
-hipError_t launch_route_accumulate(const GridHost& gh, const RouteDev& r, float* g_table, hipStream_t st) {
+hipError_t launch_route_accumulate(const GridHost& gh, const RouteDev& r, float* g_table, int64_t max_records,
+                                   hipStream_t st) {
     const uint32_t T = 1u << gh.log2_T;
     const size_t smem = ((size_t)1 << r.k) * gh.n_feat * 4;
+    // Upper bound of the chunk count (the exact one is on the device): every
+    // bucket has at most one partial chunk.
+    const unsigned blocks = (unsigned)((max_records + kRouteChunk - 1) / kRouteChunk + r.nb);
     if (gh.n_feat == 1)
-        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
     else if (gh.n_feat == 2)
-        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
     else
-        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(r.nb), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
     return hipGetLastError();
 }
 

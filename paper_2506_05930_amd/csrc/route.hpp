@@ -14,9 +14,10 @@
 //   scan      exclusive prefix of the bucket totals           route_scan_kernel
 //   emit      the training kernel writes one record per corner x-pair
 //             (the corners at dx = 0 and dx = 1 of one (dy, dz)) into its range
-//   sum       one block per partition sums its records in LDS and adds the
-//             partition to the gradient with plain, coalesced stores
-//                                                             route_accumulate_kernel
+//   sum       one block per chunk of up to kRouteChunk records of a bucket sums
+//             them in an LDS copy of the partition and adds it to the gradient:
+//             plain coalesced stores when the bucket has one chunk, line-coalesced
+//             atomics when several blocks share it      route_accumulate_kernel
 //
 // A record carries both entries of an x-pair.  On a hashed level the low 12
 // (k) bits of the hash are the only ones the x coordinate reaches when
@@ -33,6 +34,7 @@
 namespace nvc {
 
 constexpr int kRouteMaxBuckets = 8192;
+constexpr int kRouteChunk = 16384;        // records summed by one block
 
 struct RouteDev {
     int32_t enabled;
@@ -40,9 +42,10 @@ struct RouteDev {
     int32_t nb;                               // buckets over all levels
     int32_t bucket_off[kMaxLevels + 1];       // first bucket of each level
     uint32_t entries[kMaxLevels];             // entries a level uses: (N+1)^3 dense, T hashed
-    uint32_t* offsets;                        // [G][nb]: counts, then each block's offset within the bucket
+    uint32_t* offsets;                        // [nb][G]: counts, then each block's offset within the bucket
     uint32_t* totals;                         // [nb]
     uint32_t* base;                           // [nb + 1]: first record of each bucket
+    uint32_t* chunk_base;                     // [nb + 1]: first chunk (of kRouteChunk records) of each bucket
     float* vals;                              // [R][2F]: values of entry e0, then of e1
     uint32_t* keys;                           // [R]: (e0 & M) | (e1 & M) << 16, M = 2^k - 1
 };
@@ -61,6 +64,7 @@ RoutePlan make_route_plan(const GridHost& g);
 hipError_t launch_route_count(const GridHost& g, const RouteDev& r, const float* pos, const int32_t* pix,
                               int64_t batch, int grid, int pts_per_iter, hipStream_t st);
 hipError_t launch_route_prefix(const RouteDev& r, int grid, hipStream_t st);
-hipError_t launch_route_accumulate(const GridHost& g, const RouteDev& r, float* g_table, hipStream_t st);
+hipError_t launch_route_accumulate(const GridHost& g, const RouteDev& r, float* g_table, int64_t max_records,
+                                   hipStream_t st);
 
 }  // namespace nvc

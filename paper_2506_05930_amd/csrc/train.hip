@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     uint32_t* cursor = reinterpret_cast<uint32_t*>(smem_raw + TS::SMEM);
     if (a.route.enabled) {
         for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x)
-            cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)blockIdx.x * a.route.nb + i];
+            cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)i * gridDim.x + blockIdx.x];
         __syncthreads();
     }
 
@@ -485,10 +485,11 @@ bool train_supported(const GridHost& g, const NetShape& s) {
 
 // Workspace layout (each part 256-byte aligned):
 //   [G][n_w] partial weight gradients | [G] partial losses |
-//   routed scatter: [G][nb] offsets | [nb] totals | [nb+1] bases | [R][2F] values | [R] keys
+//   routed scatter: [nb][G] offsets | [nb] totals | [nb+1] bases | [nb+1] chunk bases |
+//                   [R][2F] values | [R] keys
 // with R = batch * n_levels * 4 records (one per corner x-pair).
 struct WsLayout {
-    int64_t w, loss, offsets, totals, base, vals, keys, total;
+    int64_t w, loss, offsets, totals, base, chunk_base, vals, keys, total;
 };
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -507,6 +508,8 @@ static WsLayout ws_layout(const GridHost& g, int64_t n_w, int64_t batch, int G, 
         L.totals = o;
         o = align256(o + (int64_t)rp.nb * 4);
         L.base = o;
+        o = align256(o + (int64_t)(rp.nb + 1) * 4);
+        L.chunk_base = o;
         o = align256(o + (int64_t)(rp.nb + 1) * 4);
         L.vals = o;
         o = align256(o + R * 2 * g.n_feat * 4);
@@ -580,6 +583,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         r.offsets = reinterpret_cast<uint32_t*>(ws + wl.offsets);
         r.totals = reinterpret_cast<uint32_t*>(ws + wl.totals);
         r.base = reinterpret_cast<uint32_t*>(ws + wl.base);
+        r.chunk_base = reinterpret_cast<uint32_t*>(ws + wl.chunk_base);
         r.vals = reinterpret_cast<float*>(ws + wl.vals);
         r.keys = reinterpret_cast<uint32_t*>(ws + wl.keys);
         err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
@@ -596,7 +600,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     });
     if (err != hipSuccess) return err;
     if (a.route.enabled) {
-        err = launch_route_accumulate(gh, a.route, g_table, st);
+        err = launch_route_accumulate(gh, a.route, g_table, batch * gh.n_levels * 4, st);
         if (err != hipSuccess) return err;
     }
     const int64_t nthreads = a.n_w + 1;

@@ -274,7 +274,9 @@ def test_gradients_accumulate_and_indirection():
     assert _rel_l2(cache.g_table.cpu().numpy(), 2 * ref["g_table"]) <= 1e-4
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 3e-2)])
+# A random upstream gradient makes the weight gradient a sum of terms of random
+# sign, so its FP16 relative error is larger than with loss gradients (5e-2).
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 5e-2)])
 def test_autograd_function_backward(dtype, tol):
     from paper_2506_05930_amd.cache import NVCFunction
     wl = p1080()
