@@ -135,6 +135,7 @@ def main():
            (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
     pix = torch.empty(B, dtype=torch.int32, device=dev)
     labels = torch.empty((B, wl.mlp.n_out), dtype=torch.uint8, device=dev)
+    pix_ws = cache.pixel_workspace(n_pix)
     stream = torch.cuda.current_stream()
 
     def step(frame, ev=None):
@@ -147,7 +148,7 @@ def main():
         api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
                            out["wsum"], out["di"])
         mark(2)
-        api.nvc_select_pixels(cache.seed, frame, n_pix, pix)
+        api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws)
         mark(3)
         api.nvc_shadow_labels(pos, pix, lights, spheres, labels)
         mark(4)

@@ -145,24 +145,37 @@ int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m,
                    uint64_t seed, uint32_t frame,
                    int32_t* idx, float* pmf, float* wsum, float* di, void* stream);
 
+/* Host only.  Workspace bytes nvc_select_pixels needs for an image of n_pix pixels. */
+int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix);
+
 /* Training-pixel selection (Sec. 3.4: random screen-space positions).
- * pix[b] = (r0 * n_pix) >> 32, r0 the first word of Philox4x32-10 with
- * counter (b lo32, b hi32, frame, 1) and key (seed lo32, seed hi32):
- * uniform with replacement over [0, n_pix).  pix: int32 [batch];
- * 1 <= n_pix < 2^31. */
+ * Sample b draws pixel (r0 * n_pix) >> 32, r0 the first word of
+ * Philox4x32-10 with counter (b lo32, b hi32, frame, 1) and key (seed lo32,
+ * seed hi32): uniform with replacement over [0, n_pix).  The batch is a
+ * multiset and pix (int32 [batch]) receives it in ascending order, so that
+ * consecutive samples lie on nearby surfaces (nvc_shadow_labels and
+ * nvc_train_step run faster on such batches; the training step sums over
+ * the batch, so the order does not change it).  Deterministic.
+ * workspace: nvc_select_pixels_workspace_bytes(n_pix) bytes of device memory.
+ * 1 <= n_pix < 2^31, 0 <= batch < 2^31. */
 int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch,
-                      int32_t* pix, void* stream);
+                      int32_t* pix, void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Shadow-ray labels (Sec. 3.4: one shadow ray from each training point to
  * each light) against sphere occluders.  Sample b uses position
- * pos[pix[b]] (pix may be NULL: pos[b]); pos: float32 scene units [*][3];
+ * pos[pix[b]] (pix may be NULL: pos[b]); every pix[b] must index a row of
+ * pos (device data is not validated); pos: float32 scene units [*][3];
  * lights: float32 [m][4]; spheres: float32 [n_spheres][4] = (cx, cy, cz, r).
  * labels: uint8 [n][m], 1 = visible, 0 = occluded.  A ray p -> l is occluded
  * when a sphere comes closer than r to the segment, decided in FP32 as
  *   o = c - p, cc = ((ox*ox + oy*oy) + oz*oz) - r*r, d = l - p,
  *   dd = (dx*dx + dy*dy) + dz*dz, b = (ox*dx + oy*dy) + oz*dz;
  *   b <= 0: cc < 0;  b >= dd: |c - l|^2 < r*r;  otherwise cc*dd < b*b.
- * 1 <= m <= 128; 0 <= n_spheres <= 4096. */
+ * The kernel skips spheres that provably lie farther than r from all the
+ * segments of a group of 64 samples; the labels equal the brute-force ones.
+ * Groups of nearby samples (as nvc_select_pixels returns them) run fastest.
+ * 1 <= m <= 128; 0 <= n_spheres <= 4096 (spheres, lights and their bit
+ * masks are held in at most 146 KiB of LDS). */
 int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n,
                       const float* lights, int32_t m, const float* spheres, int32_t n_spheres,
                       uint8_t* labels, void* stream);

@@ -138,11 +138,19 @@ def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tens
                                                             _stream(stream)))
 
 
-def nvc_select_pixels(seed: int, frame: int, n_pix: int, pix: torch.Tensor, stream=None) -> None:
+def nvc_select_pixels_workspace_bytes(n_pix: int) -> int:
+    return _lib.check("nvc_select_pixels_workspace_bytes", _lib.load().nvc_select_pixels_workspace_bytes(int(n_pix)))
+
+
+def nvc_select_pixels(seed: int, frame: int, n_pix: int, pix: torch.Tensor, workspace: torch.Tensor,
+                      stream=None) -> None:
     pp = _ptr(pix, "pix", torch.int32)
+    pw = _ptr(workspace, "workspace")
     _lib.check("nvc_select_pixels", _lib.load().nvc_select_pixels(int(seed) & (2 ** 64 - 1),
                                                                   int(frame) & 0xFFFFFFFF, int(n_pix),
-                                                                  pix.numel(), pp, _stream(stream)))
+                                                                  pix.numel(), pp, pw,
+                                                                  workspace.numel() * workspace.element_size(),
+                                                                  _stream(stream)))
 
 
 def nvc_shadow_labels(pos: torch.Tensor, pix, lights: torch.Tensor, spheres: torch.Tensor, labels: torch.Tensor,

@@ -64,6 +64,12 @@ class NVCache:
             self.workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         self._ws_batch = max(self._ws_batch, batch)
 
+    def pixel_workspace(self, n_pix: int) -> torch.Tensor:
+        need = api.nvc_select_pixels_workspace_bytes(n_pix)
+        if getattr(self, "_pix_ws", None) is None or self._pix_ws.numel() < need:
+            self._pix_ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._pix_ws
+
     def pack(self, stream=None):
         api.nvc_pack_mlp(self.mlp, self.w, self.packed, stream)
 
@@ -118,7 +124,8 @@ class NVCache:
         if bufs is None:
             bufs = {"pix": torch.empty(batch, dtype=torch.int32, device=self.device),
                     "labels": torch.empty((batch, self.mlp.n_out), dtype=torch.uint8, device=self.device)}
-        api.nvc_select_pixels(self.seed, frame, pos_unit.shape[0], bufs["pix"], stream)
+        api.nvc_select_pixels(self.seed, frame, pos_unit.shape[0], bufs["pix"], self.pixel_workspace(pos_unit.shape[0]),
+                              stream)
         api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
         self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
         self.adam(stream)

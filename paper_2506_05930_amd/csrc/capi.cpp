@@ -163,18 +163,24 @@ int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m, con
                                  (hipStream_t)stream));
 }
 
-int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix, void* stream) {
-    if (n_pix < 1 || n_pix >= ((int64_t)1 << 31) || batch < 0) return NVC_ERR_SHAPE;
+int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix) {
+    if (n_pix < 1 || n_pix >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
+    return select_pixels_workspace_bytes(n_pix);
+}
+
+int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix, void* workspace,
+                      int64_t workspace_bytes, void* stream) {
+    if (n_pix < 1 || n_pix >= ((int64_t)1 << 31) || batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
     if (batch == 0) return NVC_OK;
     if (!pix) return NVC_ERR_NULL;
-    return hip_status(launch_select_pixels(seed, frame, n_pix, batch, pix, (hipStream_t)stream));
+    if (!workspace || workspace_bytes < select_pixels_workspace_bytes(n_pix)) return NVC_ERR_WORKSPACE;
+    return hip_status(launch_select_pixels(seed, frame, n_pix, batch, pix, workspace, (hipStream_t)stream));
 }
 
 int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int32_t m,
                       const float* spheres, int32_t n_spheres, uint8_t* labels, void* stream) {
     if (n < 0 || m < 1 || m > 128 || n_spheres < 0 || n_spheres > 4096) return NVC_ERR_SHAPE;
-    const int64_t groups = (m + 7) / 8;
-    if ((int64_t)n_spheres * (16 + 4 * groups) > 64 * 1024) return NVC_ERR_UNSUPPORTED;
+    if (labels_smem_bytes(m, n_spheres) > 150 * 1024) return NVC_ERR_UNSUPPORTED;   // unreachable within the limits
     if (n == 0) return NVC_OK;
     if (!pos || !lights || !labels || (n_spheres > 0 && !spheres)) return NVC_ERR_NULL;
     return hip_status(launch_labels(pos, pix, n, lights, m, spheres, n_spheres, labels, (hipStream_t)stream));

@@ -154,6 +154,7 @@ struct InferArgs {
     int vis_dtype;
     int act;
     float slope;
+    int vec_ok;           // rows start 4-element aligned and vis is 16-byte aligned: vector stores
 };
 
 template <class C>
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = sigmoidf_(z[s][ob][i]);
                 const int64_t base = p * a.n_out + l0;
-                if (l0 + 4 <= a.n_out && (a.n_out & 3) == 0) {
+                if (a.vec_ok && l0 + 4 <= a.n_out) {
                     if (a.vis_dtype == DT_F32) {
                         *reinterpret_cast<float4*>((float*)a.vis + base) = make_float4(v[0], v[1], v[2], v[3]);
                     } else if (a.vis_dtype == DT_F16) {
@@ -305,6 +306,7 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     a.vis_dtype = vis_dtype;
     a.act = act;
     a.slope = slope;
+    a.vec_ok = (n_out % 4) == 0 && ((uintptr_t)vis % 16) == 0;
     using LY = FwdLayout<C>;
     const size_t wbytes = (size_t)LY::total * sizeof(typename Mma<C::DT>::elem);
     const size_t smem = wbytes <= (size_t)kInferLdsMax ? wbytes : 0;

@@ -61,8 +61,10 @@ bool infer_supported(const GridHost& g, const NetShape& s);
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
                       const float* lights, float vis_floor, uint64_t seed, uint32_t frame, int32_t* idx,
                       float* pmf, float* wsum, float* di, hipStream_t st);
+int64_t select_pixels_workspace_bytes(int64_t n_pix);
 hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix,
-                                hipStream_t st);
+                                void* workspace, hipStream_t st);
+size_t labels_smem_bytes(int m, int n_spheres);
 hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
                          const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st);
 bool train_supported(const GridHost& g, const NetShape& s);

@@ -83,7 +83,9 @@ def test_param_counts(lib):
 
 
 def test_calls_reject_bad_arguments_before_launching(lib):
-    P = ctypes.c_void_p(16)             # never dereferenced: validation fails first
+    # P is never dereferenced: every call below must fail validation (or be a no-op)
+    # before anything is launched.  Never pass it to a call that would launch.
+    P = ctypes.c_void_p(16)
     N = None
     gg, mm = ctypes.byref(g()), ctypes.byref(m())
     assert lib.nvc_encode(None, P, P, 10, P, 0, N) == _lib.NVC_ERR_NULL
@@ -100,12 +102,18 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_DTYPE
-    assert lib.nvc_select_pixels(0, 0, 0, 10, P, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_select_pixels(0, 0, 1 << 31, 10, P, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_select_pixels(0, 0, 100, 10, None, N) == _lib.NVC_ERR_NULL
+    ws = lib.nvc_select_pixels_workspace_bytes(100)
+    assert ws >= 800
+    assert lib.nvc_select_pixels_workspace_bytes(0) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, 0, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, 1 << 31, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, 100, 10, None, P, ws, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_select_pixels(0, 0, 100, 10, P, P, ws - 1, N) == _lib.NVC_ERR_WORKSPACE
+    assert lib.nvc_select_pixels(0, 0, 100, 10, P, None, ws, N) == _lib.NVC_ERR_WORKSPACE
     assert lib.nvc_shadow_labels(P, N, 10, P, 0, P, 1, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels(P, N, 10, P, 32, None, 4, P, N) == _lib.NVC_ERR_NULL
-    assert lib.nvc_shadow_labels(P, N, 10, P, 128, P, 4000, P, N) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_shadow_labels(P, N, 10, P, 128, P, 4097, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_shadow_labels(P, N, -1, P, 32, P, 16, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_adam(P, P, P, P, 10, 0, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_adam(P, P, P, P, 10, 1, 1e-2, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_adam(None, P, P, P, 10, 1, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL

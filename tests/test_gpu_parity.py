@@ -192,11 +192,14 @@ def test_wrs_all_lights_behind_surface():
 
 # ----------------------------------------------------------------- training inputs
 def test_select_pixels_bit_exact():
+    """The batch is the oracle's multiset of Philox pixel draws, returned sorted."""
     from paper_2506_05930_amd import api
-    for n_pix, batch, frame in ((1920 * 1080, 1 << 18, 3), (1000, 5000, 0), (1, 7, 9)):
+    for n_pix, batch, frame in ((1920 * 1080, 1 << 18, 3), (1000, 5000, 0), (1, 7, 9), (4097, 300, 1)):
         pix = torch.empty(batch, dtype=torch.int32, device=DEV)
-        api.nvc_select_pixels(2, frame, n_pix, pix)
-        assert np.array_equal(pix.cpu().numpy(), philox.training_pixels(2, frame, batch, n_pix))
+        ws = torch.empty(api.nvc_select_pixels_workspace_bytes(n_pix), dtype=torch.uint8, device=DEV)
+        ws.fill_(0xAB)                             # stale contents must not matter
+        api.nvc_select_pixels(2, frame, n_pix, pix, ws)
+        assert np.array_equal(pix.cpu().numpy(), np.sort(philox.training_pixels(2, frame, batch, n_pix)))
 
 
 @pytest.mark.parametrize("m", [8, 32, 128, 13])
@@ -208,6 +211,8 @@ def test_shadow_labels_bit_exact(small_scene, m):
     n_pix = sc["pos"].shape[0]
     batch = 3001
     pix = philox.training_pixels(2, 1, batch, n_pix).astype(np.int32)
+    if m != 13:
+        pix = np.sort(pix)                      # grouped samples: sphere culling active
     lab = torch.empty((batch, m), dtype=torch.uint8, device=DEV)
     api.nvc_shadow_labels(t(sc["pos"]), t(pix), t(lights), t(sc["spheres"]), lab)
     ref = shadow.labels_fp32(sc["pos"][pix], lights, sc["spheres"])
