@@ -127,23 +127,42 @@ hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, in
 // ------------------------------------------------------------------ shadow labels
 __device__ inline uint32_t float_key(float v) { return __float_as_uint(v); }   // order-preserving for v >= 0
 
-__global__ __launch_bounds__(256) void labels_kernel(const float* __restrict__ pos, const int32_t* __restrict__ pix,
-                                                     int64_t n, const float* __restrict__ lights, int m,
-                                                     const float* __restrict__ spheres, int n_spheres,
-                                                     uint8_t* __restrict__ labels) {
+__device__ inline uint32_t spread10(uint32_t v) {        // 10 bits -> every third bit of 30
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+constexpr int kLabelBlock = 1024;   // samples per block (16 waves of 64)
+constexpr int kLabelLights = 8;     // lights per block (grid.y covers all lights)
+
+// Block (x, y): samples [x*1024, x*1024 + 1024) and lights [8y, 8y + 8).  The
+// block sorts its samples by the 3D Morton code of their position inside the
+// block's bounding box, so each wave of 64 consecutive sorted samples is
+// compact in space (samples on both sides of a depth edge go to different
+// waves); labels are written at the samples' own rows.
+__global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ pos, const int32_t* __restrict__ pix,
+                                                      int64_t n, const float* __restrict__ lights, int m,
+                                                      const float* __restrict__ spheres, int n_spheres,
+                                                      uint8_t* __restrict__ labels) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     float4* S = reinterpret_cast<float4*>(smem_raw);                          // (cx, cy, cz, r*r)
     float* R = reinterpret_cast<float*>(S + n_spheres);                       // r
-    float4* Lg = reinterpret_cast<float4*>(R + ((n_spheres + 3) & ~3));       // (lx, ly, lz, 0)
-    const int lw = (m + 31) / 32;                                             // words of light bits
-    uint32_t* inside = reinterpret_cast<uint32_t*>(Lg + m);                   // [n_spheres][lw]
+    float4* Lg = reinterpret_cast<float4*>(R + ((n_spheres + 3) & ~3));       // this block's lights
+    uint32_t* inside = reinterpret_cast<uint32_t*>(Lg + kLabelLights);        // [n_spheres]: bit i = light 8y+i
+    __shared__ uint64_t keys[kLabelBlock];
     __shared__ uint32_t scale_bits;
+    const int l0 = blockIdx.y * kLabelLights;
+    const int nl = min(kLabelLights, m - l0);
     if (threadIdx.x == 0) scale_bits = 0;
     __syncthreads();
     uint32_t my_scale = 0;
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
         const float lx = lights[4 * j + 0], ly = lights[4 * j + 1], lz = lights[4 * j + 2];
-        Lg[j] = make_float4(lx, ly, lz, 0.0f);
+        if (j >= l0 && j < l0 + nl) Lg[j - l0] = make_float4(lx, ly, lz, 0.0f);
         my_scale = max(my_scale, float_key(fmaxf(fabsf(lx), fmaxf(fabsf(ly), fabsf(lz)))));
     }
     for (int s = threadIdx.x; s < n_spheres; s += blockDim.x) {
@@ -152,21 +171,91 @@ __global__ __launch_bounds__(256) void labels_kernel(const float* __restrict__ p
         S[s] = make_float4(cx, cy, cz, rr);
         R[s] = r;
         my_scale = max(my_scale, float_key(fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz))) + fabsf(r)));
-        for (int w = 0; w < lw; ++w) {
-            uint32_t bits = 0;
-            for (int j = 0; j < 32 && 32 * w + j < m; ++j) {
-                const int li = 32 * w + j;
-                const float ex = cx - lights[4 * li + 0], ey = cy - lights[4 * li + 1], ez = cz - lights[4 * li + 2];
-                if (((ex * ex + ey * ey) + ez * ez) < rr) bits |= 1u << j;
-            }
-            inside[s * lw + w] = bits;
+        uint32_t bits = 0;
+        for (int i = 0; i < nl; ++i) {
+            const int li = l0 + i;
+            const float ex = cx - lights[4 * li + 0], ey = cy - lights[4 * li + 1], ez = cz - lights[4 * li + 2];
+            if (((ex * ex + ey * ey) + ez * ez) < rr) bits |= 1u << i;
         }
+        inside[s] = bits;
+    }
+
+    // This thread's sample (unsorted) and the block's bounding box.
+    const int64_t b_own = (int64_t)blockIdx.x * kLabelBlock + threadIdx.x;
+    const bool own_valid = b_own < n;
+    float ox0 = 0.f, oy0 = 0.f, oz0 = 0.f;
+    if (own_valid) {
+        const int64_t src = pix ? (int64_t)pix[b_own] : b_own;
+        ox0 = pos[src * 3 + 0];
+        oy0 = pos[src * 3 + 1];
+        oz0 = pos[src * 3 + 2];
     }
     atomicMax(&scale_bits, my_scale);
+    // Block bounding box of the finite samples (NaN / Inf samples sort last).
+    __shared__ float bmin[3], bmax[3];
+    if (threadIdx.x < 3) { bmin[threadIdx.x] = INFINITY; bmax[threadIdx.x] = -INFINITY; }
     __syncthreads();
+    const bool fin = own_valid && isfinite(ox0) && isfinite(oy0) && isfinite(oz0);
+    {
+        float mn[3] = {fin ? ox0 : INFINITY, fin ? oy0 : INFINITY, fin ? oz0 : INFINITY};
+        float mx[3] = {fin ? ox0 : -INFINITY, fin ? oy0 : -INFINITY, fin ? oz0 : -INFINITY};
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            for (int off = 32; off > 0; off >>= 1) {
+                mn[k] = fminf(mn[k], __shfl_xor(mn[k], off));
+                mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
+            }
+        __shared__ float wmn[16][3], wmx[16][3];
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            for (int k = 0; k < 3; ++k) { wmn[w][k] = mn[k]; wmx[w][k] = mx[k]; }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            float a = INFINITY, c = -INFINITY;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { a = fminf(a, wmn[i][threadIdx.x]); c = fmaxf(c, wmx[i][threadIdx.x]); }
+            bmin[threadIdx.x] = a;
+            bmax[threadIdx.x] = c;
+        }
+        __syncthreads();
+    }
+    // Morton key inside the box; invalid or non-finite samples get the largest keys.
+    {
+        uint64_t key;
+        if (fin) {
+            uint32_t q[3];
+            const float v[3] = {ox0, oy0, oz0};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float ext = bmax[k] - bmin[k];
+                const float t = ext > 0.0f ? (v[k] - bmin[k]) / ext : 0.0f;
+                q[k] = (uint32_t)fminf(fmaxf(t * 1023.0f, 0.0f), 1023.0f);
+            }
+            key = (uint64_t)(spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2)) << 11;
+        } else {
+            key = (own_valid ? (1ull << 41) : (1ull << 42));
+        }
+        keys[threadIdx.x] = key | (uint64_t)threadIdx.x;
+    }
+    __syncthreads();
+    // Bitonic sort of the 1024 keys in LDS.
+    for (int k = 2; k <= kLabelBlock; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            const int i = threadIdx.x, ixj = i ^ jj;
+            if (ixj > i) {
+                const uint64_t a = keys[i], c = keys[ixj];
+                const bool up = (i & k) == 0;
+                if ((a > c) == up) {
+                    keys[i] = c;
+                    keys[ixj] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
 
     const int lane = threadIdx.x & 63;
-    const int64_t b = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64 + lane;
+    const int local = (int)(keys[threadIdx.x] & 1023u);
+    const int64_t b = (int64_t)blockIdx.x * kLabelBlock + local;
     const bool valid = b < n;
     const int64_t src = valid ? (pix ? (int64_t)pix[b] : b) : 0;
     const float px = valid ? pos[src * 3 + 0] : 0.0f;
@@ -190,81 +279,91 @@ __global__ __launch_bounds__(256) void labels_kernel(const float* __restrict__ p
     const float rho = sqrtf(hx * hx + hy * hy + hz * hz) * 1.0001f;
     const float scale = fmaxf(__uint_as_float(scale_bits), fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz))) + rho);
     const float margin = 1e-3f * (1.0f + scale);
-
     // With a non-finite bounding box, nothing is culled (the exact test alone decides).
     const bool cull_ok = isfinite(rho) && isfinite(cx) && isfinite(cy) && isfinite(cz) && isfinite(margin);
-    uint8_t* out = labels + (valid ? b : 0) * (int64_t)m;
-    for (int j0 = 0; j0 < m; j0 += 32) {
-        uint32_t word = 0;                       // bit i: light j0 + i is visible
-        const int jn = min(32, m - j0);
-        for (int i = 0; i < jn; ++i) {
-            const int j = j0 + i;
-            const float4 l = Lg[j];
-            const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
-            const float dd = (dx * dx + dy * dy) + dz * dz;
-            const float gx = l.x - cx, gy = l.y - cy, gz = l.z - cz;            // bundle axis pbar -> l
-            const float gg = gx * gx + gy * gy + gz * gz;
-            const float ginv = gg > 0.0f ? 1.0f / gg : 0.0f;
-            bool occ = false;
-            for (int c0 = 0; c0 < n_spheres; c0 += 64) {
-                const int s = c0 + lane;
-                bool keep = false;
-                if (s < n_spheres) {
-                    const float4 sc = S[s];
-                    const float ox = sc.x - cx, oy = sc.y - cy, oz = sc.z - cz;
-                    const float t = fminf(fmaxf((ox * gx + oy * gy + oz * gz) * ginv, 0.0f), 1.0f);
-                    const float qx = ox - t * gx, qy = oy - t * gy, qz = oz - t * gz;
-                    const float lim = R[s] + rho + margin;
-                    keep = !cull_ok || qx * qx + qy * qy + qz * qz <= lim * lim;
-                }
-                uint64_t mask = __ballot(keep);
-                while (mask) {
-                    const int s2 = c0 + __builtin_ctzll(mask);
+
+    uint32_t word = 0;                                   // bit i: light l0 + i is visible
+    for (int i = 0; i < nl; ++i) {
+        const float4 l = Lg[i];
+        const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
+        const float dd = (dx * dx + dy * dy) + dz * dz;
+        const float gx = l.x - cx, gy = l.y - cy, gz = l.z - cz;                // bundle axis pbar -> l
+        const float gg = gx * gx + gy * gy + gz * gz;
+        const float ginv = gg > 0.0f ? 1.0f / gg : 0.0f;
+        uint32_t occ_bits = 0;
+        for (int c0 = 0; c0 < n_spheres; c0 += 64) {
+            const int s = c0 + lane;
+            bool keep = false;
+            if (s < n_spheres) {
+                const float4 sc = S[s];
+                const float ox = sc.x - cx, oy = sc.y - cy, oz = sc.z - cz;
+                const float t = fminf(fmaxf((ox * gx + oy * gy + oz * gz) * ginv, 0.0f), 1.0f);
+                const float qx = ox - t * gx, qy = oy - t * gy, qz = oz - t * gz;
+                const float lim = R[s] + rho + margin;
+                keep = !cull_ok || qx * qx + qy * qy + qz * qz <= lim * lim;
+            }
+            uint64_t mask = __ballot(keep);
+            // Survivors in groups of four (a short group repeats its last sphere; a
+            // repeated test leaves the OR unchanged): all LDS reads are issued before
+            // the tests, and the test is branch-free.
+            while (mask) {
+                int sq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sq[q] = mask ? c0 + __builtin_ctzll(mask) : sq[q > 0 ? q - 1 : 0];
                     mask &= mask - 1;
-                    const float4 sc = S[s2];
-                    const float ox = sc.x - px, oy = sc.y - py, oz = sc.z - pz;
-                    const float cc = ((ox * ox + oy * oy) + oz * oz) - sc.w;
+                }
+                float4 sc[4];
+                uint32_t ib[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    sc[q] = S[sq[q]];
+                    ib[q] = inside[sq[q]];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float ox = sc[q].x - px, oy = sc[q].y - py, oz = sc[q].z - pz;
+                    const float cc = ((ox * ox + oy * oy) + oz * oz) - sc[q].w;
                     const float bb = (ox * dx + oy * dy) + oz * dz;
-                    bool o;
-                    if (bb <= 0.0f)
-                        o = cc < 0.0f;
-                    else if (bb >= dd)
-                        o = (inside[s2 * lw + (j >> 5)] >> (j & 31)) & 1u;
-                    else
-                        o = cc * dd < bb * bb;
-                    occ = occ || o;
+                    // closest point p (bb <= 0): p inside; the light (bb >= dd): light inside;
+                    // otherwise the interior test, as bit arithmetic (no divergent branches)
+                    const uint32_t near_p = bb <= 0.0f;
+                    const uint32_t near_l = (bb >= dd) & ~near_p;
+                    const uint32_t mid = ~(near_p | near_l) & 1u;
+                    const uint32_t o = (near_p & (uint32_t)(cc < 0.0f)) | (near_l & (ib[q] >> i)) |
+                                       (mid & (uint32_t)(cc * dd < bb * bb));
+                    occ_bits |= o;
                 }
             }
-            if (!occ) word |= 1u << i;
         }
-        if (!valid) continue;
-        if (jn == 32 && ((uintptr_t)(out + j0) & 15u) == 0) {   // 32 labels as two 16-byte stores
-            uint32_t w8[8];
+        if (!(occ_bits & 1u)) word |= 1u << i;
+    }
+    if (!valid) return;
+    uint8_t* out = labels + b * (int64_t)m + l0;
+    if (nl == 8 && ((uintptr_t)out & 7u) == 0) {
+        uint32_t w0 = 0, w1 = 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v |= ((word >> (4 * q + i)) & 1u) << (8 * i);
-                w8[q] = v;
-            }
-            *reinterpret_cast<uint4*>(out + j0) = make_uint4(w8[0], w8[1], w8[2], w8[3]);
-            *reinterpret_cast<uint4*>(out + j0 + 16) = make_uint4(w8[4], w8[5], w8[6], w8[7]);
-        } else {
-            for (int i = 0; i < jn; ++i) out[j0 + i] = (uint8_t)((word >> i) & 1u);
+        for (int i = 0; i < 4; ++i) {
+            w0 |= ((word >> i) & 1u) << (8 * i);
+            w1 |= ((word >> (4 + i)) & 1u) << (8 * i);
         }
+        *reinterpret_cast<uint2*>(out) = make_uint2(w0, w1);
+    } else {
+        for (int i = 0; i < nl; ++i) out[i] = (uint8_t)((word >> i) & 1u);
     }
 }
 
 size_t labels_smem_bytes(int m, int n_spheres) {
-    const int lw = (m + 31) / 32;
-    return (size_t)n_spheres * 16 + (size_t)((n_spheres + 3) & ~3) * 4 + (size_t)m * 16 + (size_t)n_spheres * lw * 4;
+    (void)m;
+    return (size_t)n_spheres * 16 + (size_t)((n_spheres + 3) & ~3) * 4 + (size_t)kLabelLights * 16 +
+           (size_t)n_spheres * 4;
 }
 
 hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
                          const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st) {
     const size_t smem = labels_smem_bytes(m, n_spheres);
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(labels_kernel, dim3(blocks), dim3(256), smem, st, pos, pix, n, lights, m, spheres, n_spheres,
+    const dim3 grid((unsigned)((n + kLabelBlock - 1) / kLabelBlock), (unsigned)((m + kLabelLights - 1) / kLabelLights));
+    hipLaunchKernelGGL(labels_kernel, grid, dim3(kLabelBlock), smem, st, pos, pix, n, lights, m, spheres, n_spheres,
                        labels);
     return hipGetLastError();
 }

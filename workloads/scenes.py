@@ -107,10 +107,32 @@ def _cast(eye, d, boxes_lo, boxes_hi):
     return t_best, nrm
 
 
+def morton_order(width: int, height: int) -> np.ndarray:
+    """Row-major pixel indices listed in Z-order (Morton) of (x, y): any run of consecutive
+    entries covers a compact 2D block of the image, as in tiled G-buffer layouts."""
+    x = np.tile(np.arange(width, dtype=np.uint64), height)
+    y = np.repeat(np.arange(height, dtype=np.uint64), width)
+
+    def spread(v):
+        v = (v | (v << np.uint64(16))) & np.uint64(0x0000FFFF0000FFFF)
+        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF00FF00FF)
+        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F0F0F0F0F)
+        v = (v | (v << np.uint64(2))) & np.uint64(0x3333333333333333)
+        v = (v | (v << np.uint64(1))) & np.uint64(0x5555555555555555)
+        return v
+
+    key = spread(x) | (spread(y) << np.uint64(1))
+    return np.argsort(key, kind="stable")
+
+
 def box_scene(seed: int, width: int, height: int, n_boxes: int, n_lights: int, n_spheres: int,
               eye=(9.5, 5.0, 9.5), target=(0.0, 3.0, 0.0), vfov_deg: float = 50.0,
-              chunk_rows: int = 16) -> dict:
-    """Box room G-buffer: pos/nrm float32 [H*W, 3] in scene units, row-major pixels.
+              chunk_rows: int = 16, order: str = "morton") -> dict:
+    """Box room G-buffer: pos/nrm float32 [H*W, 3] in scene units.
+
+    order='morton' (default) stores the pixels in Z-order of their (x, y) image
+    coordinates; order='rows' keeps row-major order.  `pixel_xy` [H*W, 2] gives
+    the image coordinates of every stored pixel.
 
     Draw order: box min corners U[0,9]^3, box extents U(0.3,1.5)^3 (clipped to
     the room), spheres (centres U[0,10]^3, radius U(0.1,0.8)), lights
@@ -139,9 +161,18 @@ def box_scene(seed: int, width: int, height: int, n_boxes: int, n_lights: int, n
     # Rows are independent and numpy releases the GIL, so a thread pool is deterministic and faster.
     with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
         list(ex.map(render, range(0, height, chunk_rows)))
+    if order == "morton":
+        perm = morton_order(width, height)
+    elif order == "rows":
+        perm = np.arange(width * height)
+    else:
+        raise ValueError(order)
+    pos = np.ascontiguousarray(pos[perm])
+    nrm = np.ascontiguousarray(nrm[perm])
+    xy = np.stack([perm % width, perm // width], axis=1).astype(np.int32)
     return {"pos": pos, "nrm": nrm, "pos_unit": pos_to_unit(pos, SCENE_EXTENT), "lights": lights,
             "spheres": spheres, "boxes": np.concatenate([lo, hi], axis=1).astype(np.float32),
-            "extent": SCENE_EXTENT}
+            "extent": SCENE_EXTENT, "pixel_xy": xy, "order": order}
 
 
 def pos_to_unit(pos: np.ndarray, extent: float = SCENE_EXTENT) -> np.ndarray:
