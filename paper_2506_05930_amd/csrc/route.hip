@@ -41,6 +41,9 @@ RoutePlan make_route_plan(const GridHost& g) {
 
 // Counts the records each training block will emit, per bucket.  Block j owns
 // the same samples as training block j: b = it * P + t for it = j, j + G, ...
+// A wave holds 64 consecutive samples of one level; runs of equal corner
+// x-pairs within aligned groups of 16 samples count once, as the training
+// kernel merges them.
 template <int F>
 __global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r, const float* __restrict__ pos,
                                                          const int32_t* __restrict__ pix, int64_t batch, int P) {
@@ -49,26 +52,29 @@ __global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r,
     __syncthreads();
     const int64_t iters = (batch + P - 1) / P;
     const uint32_t M = (1u << r.k) - 1u;
-    const int lanes_per_level_set = 2;                       // thread halves split the levels
-    const int t = threadIdx.x % (blockDim.x / lanes_per_level_set);
-    const int half = threadIdx.x / (blockDim.x / lanes_per_level_set);
+    const int per_half = blockDim.x / 2;                     // P = 128 samples, two level parities
+    const int t = threadIdx.x % per_half;
+    const int half = threadIdx.x / per_half;
+    const int col = threadIdx.x & 15;
     for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
-        for (int s = t; s < P; s += blockDim.x / lanes_per_level_set) {
-            const int64_t b = it * P + s;
-            if (b >= batch) continue;
-            const int64_t src = pix ? (int64_t)pix[b] : b;
-            const float x = clamp_unit(pos[src * 3 + 0]);
-            const float y = clamp_unit(pos[src * 3 + 1]);
-            const float z = clamp_unit(pos[src * 3 + 2]);
-            for (int l = half; l < g.n_levels; l += lanes_per_level_set) {
+        for (int s0 = 0; s0 < P; s0 += per_half) {
+            const int64_t b = it * P + s0 + t;
+            const bool valid = b < batch;
+            const int64_t src = valid ? (pix ? (int64_t)pix[b] : b) : 0;
+            const float x = valid ? clamp_unit(pos[src * 3 + 0]) : 0.0f;
+            const float y = valid ? clamp_unit(pos[src * 3 + 1]) : 0.0f;
+            const float z = valid ? clamp_unit(pos[src * 3 + 2]) : 0.0f;
+            for (int l = half; l < g.n_levels; l += 2) {
                 Corners cr;
                 level_corners(g, l, x, y, z, cr);
                 const bool dense = (g.dense_mask >> l) & 1u;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
-                    const uint32_t e0 = cr.idx[2 * p];
-                    if (dense && (e0 & M) == M) continue;          // straddler: direct atomics
-                    atomicAdd(&hist[r.bucket_off[l] + (e0 >> r.k)], 1u);
+                    const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
+                    const bool part = valid && !(dense && (e0 & M) == M);
+                    const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)(threadIdx.x & 63);
+                    const RunInfo ri = row_runs(k0, k1, col);
+                    if (part && ri.head) atomicAdd(&hist[r.bucket_off[l] + (e0 >> r.k)], 1u);
                 }
             }
         }
@@ -144,23 +150,26 @@ __global__ __launch_bounds__(1024) void route_scan_kernel(RouteDev r) {
         r.base[r.nb] = part[1023];
         r.chunk_base[r.nb] = cpart[1023];
     }
+    // chunk -> bucket table for the partition sums
+    crun = cpart[t] - csum;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int b = t * PER + i;
+        for (uint32_t q = 0; q < c[i]; ++q) r.chunk_bucket[crun + q] = (uint32_t)b;
+        crun += c[i];
+    }
 }
 
 // One block per chunk of a bucket: sum the chunk's records into an LDS copy of
 // the partition, then add it to the gradient (plain stores if the bucket has a
 // single chunk, atomics otherwise; 16 lanes cover one 64-byte line).
 template <int F>
-__global__ __launch_bounds__(256) void route_accumulate_kernel(RouteDev r, int n_levels, uint32_t T,
+__global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n_levels, uint32_t T,
                                                               float* __restrict__ g_table) {
     extern __shared__ float part[];
     const uint32_t c = blockIdx.x;
     if (c >= r.chunk_base[r.nb]) return;
-    int lo = 0, hi = r.nb;                                   // bucket b: chunk_base[b] <= c < chunk_base[b+1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (r.chunk_base[mid] <= c) lo = mid; else hi = mid;
-    }
-    const int b = lo;
+    const int b = (int)r.chunk_bucket[c];
     int l = 0;
     while (l + 1 < n_levels && r.bucket_off[l + 1] <= b) ++l;
     const uint32_t ps = 1u << r.k;
@@ -172,22 +181,37 @@ __global__ __launch_bounds__(256) void route_accumulate_kernel(RouteDev r, int n
     const uint32_t r1 = min(r.base[b + 1], r0 + (uint32_t)kRouteChunk);
     for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0.0f;
     __syncthreads();
-    for (uint32_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-        const uint32_t key = r.keys[i];
-        const uint32_t lo0 = key & 0xFFFFu, lo1 = key >> 16;
-        const float* v = r.vals + (size_t)i * (2 * F);
-        float w[2 * F];
-        if constexpr (F == 2) {
-            const float4 qv = *reinterpret_cast<const float4*>(v);
-            w[0] = qv.x; w[1] = qv.y; w[2] = qv.z; w[3] = qv.w;
-        } else {
+    // Four records per thread and step, all loads issued before the LDS adds.
+    constexpr int U = 4;
+    for (uint32_t i0 = r0 + threadIdx.x; i0 < r1; i0 += U * blockDim.x) {
+        uint32_t key[U];
+        float w[U][2 * F];
 #pragma unroll
-            for (int j = 0; j < 2 * F; ++j) w[j] = v[j];
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = i0 + u * blockDim.x;
+            const bool ok = i < r1;
+            key[u] = ok ? r.keys[i] : 0u;
+            const float* v = r.vals + (size_t)(ok ? i : r0) * (2 * F);
+            if constexpr (F == 2) {
+                const float4 qv = *reinterpret_cast<const float4*>(v);
+                w[u][0] = qv.x; w[u][1] = qv.y; w[u][2] = qv.z; w[u][3] = qv.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 2 * F; ++j) w[u][j] = v[j];
+            }
+            if (!ok) {
+#pragma unroll
+                for (int j = 0; j < 2 * F; ++j) w[u][j] = 0.0f;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < F; ++j) {
-            atomicAdd(&part[lo0 * F + j], w[j]);
-            atomicAdd(&part[lo1 * F + j], w[F + j]);
+        for (int u = 0; u < U; ++u) {
+            const uint32_t lo0 = key[u] & 0xFFFFu, lo1 = key[u] >> 16;
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                atomicAdd(&part[lo0 * F + j], w[u][j]);
+                atomicAdd(&part[lo1 * F + j], w[u][F + j]);
+            }
         }
     }
     __syncthreads();
@@ -229,11 +253,11 @@ hipError_t launch_route_accumulate(const GridHost& gh, const RouteDev& r, float*
     // bucket has at most one partial chunk.
     const unsigned blocks = (unsigned)((max_records + kRouteChunk - 1) / kRouteChunk + r.nb);
     if (gh.n_feat == 1)
-        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
     else if (gh.n_feat == 2)
-        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
     else
-        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(blocks), dim3(256), smem, st, r, gh.n_levels, T, g_table);
+        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
     return hipGetLastError();
 }
 

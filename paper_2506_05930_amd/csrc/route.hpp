@@ -46,9 +46,47 @@ struct RouteDev {
     uint32_t* totals;                         // [nb]
     uint32_t* base;                           // [nb + 1]: first record of each bucket
     uint32_t* chunk_base;                     // [nb + 1]: first chunk (of kRouteChunk records) of each bucket
+    uint32_t* chunk_bucket;                   // [max chunks]: bucket of every chunk
     float* vals;                              // [R][2F]: values of entry e0, then of e1
     uint32_t* keys;                           // [R]: (e0 & M) | (e1 & M) << 16, M = 2^k - 1
 };
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Runs of equal keys among the 16 lanes of a row (lanes 16r .. 16r+15 hold 16
+// consecutive samples): `head` marks the first lane of a run, `last` the last.
+struct RunInfo {
+    bool head;
+    bool last;
+};
+
+__device__ inline RunInfo row_runs(uint32_t k0, uint32_t k1, int col) {
+    const uint32_t p0 = __shfl_up(k0, 1, 16), p1 = __shfl_up(k1, 1, 16);
+    const uint32_t n0 = __shfl_down(k0, 1, 16), n1 = __shfl_down(k1, 1, 16);
+    RunInfo r;
+    r.head = col == 0 || p0 != k0 || p1 != k1;
+    r.last = col == 15 || n0 != k0 || n1 != k1;
+    return r;
+}
+
+// Reverse segmented sum within the row: afterwards each lane holds the sum of
+// its own value and those of the later lanes of its run (the head: the run).
+template <int NV>
+__device__ inline void row_run_sums(float (&v)[NV], bool last, int col) {
+    bool e = last;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+        float o[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) o[j] = __shfl_down(v[j], d, 16);
+        const bool eo = col + d < 16 ? (bool)__shfl_down((int)e, d, 16) : true;
+        if (!e && col + d < 16) {
+#pragma unroll
+            for (int j = 0; j < NV; ++j) v[j] += o[j];
+        }
+        e = e || eo;
+    }
+}
+#endif
 
 // Host-side plan: partition size, bucket numbering, whether routing applies.
 struct RoutePlan {

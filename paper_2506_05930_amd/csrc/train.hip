@@ -221,11 +221,15 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     const int col = lane & 15;
     const E* packed = reinterpret_cast<const E*>(a.packed);
 
-    // Write cursors of the routed scatter: this block's range in every bucket.
+    // Write cursors of the routed scatter: this block's range [cursor, cursor_end) in every bucket.
     uint32_t* cursor = reinterpret_cast<uint32_t*>(smem_raw + TS::SMEM);
+    uint32_t* cursor_end = cursor + (a.route.enabled ? a.route.nb : 0);
     if (a.route.enabled) {
-        for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x)
-            cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)i * gridDim.x + blockIdx.x];
+        for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x) {
+            const uint32_t* row = a.route.offsets + (int64_t)i * gridDim.x;
+            cursor[i] = a.route.base[i] + row[blockIdx.x];
+            cursor_end[i] = a.route.base[i] + (blockIdx.x + 1 < gridDim.x ? row[blockIdx.x + 1] : a.route.totals[i]);
+        }
         __syncthreads();
     }
 
@@ -356,25 +360,30 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
         });
 
         // ---------------- hash-table gradient ----------------
+        // Lane (grp, col) holds sample col of the sub-tile for the levels of
+        // group grp, so each 16-lane row covers 16 consecutive samples of one
+        // level.  With the routed scatter, equal corner x-pairs of consecutive
+        // samples (frequent on coarse levels) are summed across the row first
+        // and only the first lane of each run writes a record.
 #pragma unroll
         for (int s = 0; s < kTrainSub; ++s) {
-            if (!valid[s]) continue;
 #pragma unroll
             for (int b = 0; b < C::NINB; ++b) {
 #pragma unroll
                 for (int q = 0; q < 4; q += C::F) {
                     const int feat = 16 * b + 4 * grp + q;
                     const int l = feat / C::F;
-                    if (l >= a.g.n_levels) continue;
+                    const bool lvl_ok = l < a.g.n_levels;
+                    if (!a.route.enabled && (!valid[s] || !lvl_ok)) continue;
                     Corners cr;
-                    level_corners(a.g, l, x[s][0], x[s][1], x[s][2], cr);
-                    float* gl = a.g_table + (size_t)l * a.g.T * C::F;
+                    level_corners(a.g, lvl_ok ? l : 0, x[s][0], x[s][1], x[s][2], cr);
+                    float* gl = a.g_table + (size_t)(lvl_ok ? l : 0) * a.g.T * C::F;
                     float dj[C::F];
 #pragma unroll
                     for (int j = 0; j < C::F; ++j) dj[j] = denc[s][b][q + j] * a.final_mul;
                     if (a.route.enabled) {
                         const uint32_t M = (1u << a.route.k) - 1u;
-                        const bool dense = (a.g.dense_mask >> l) & 1u;
+                        const bool dense = lvl_ok && ((a.g.dense_mask >> l) & 1u);
 #pragma unroll
                         for (int p = 0; p < 4; ++p) {
                             const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
@@ -384,23 +393,43 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
                                 v[j] = cr.w[2 * p] * dj[j];
                                 v[C::F + j] = cr.w[2 * p + 1] * dj[j];
                             }
-                            if (dense && (e0 & M) == M) {          // pair straddles two partitions
+                            const bool straddle = dense && (e0 & M) == M;   // pair spans two partitions
+                            if (valid[s] && lvl_ok && straddle) {
 #pragma unroll
                                 for (int j = 0; j < C::F; ++j) {
                                     unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
                                     unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
                                 }
-                                continue;
                             }
-                            const uint32_t slot = atomicAdd(&cursor[a.route.bucket_off[l] + (e0 >> a.route.k)], 1u);
-                            float* dst = a.route.vals + (size_t)slot * (2 * C::F);
-                            if constexpr (C::F == 2) {
-                                *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-                            } else {
+                            const bool part = valid[s] && lvl_ok && !straddle;
+                            // Keys of lanes that do not take part differ from every real key.
+                            const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)lane;
+                            if (!part) {
 #pragma unroll
-                                for (int j = 0; j < 2 * C::F; ++j) dst[j] = v[j];
+                                for (int j = 0; j < 2 * C::F; ++j) v[j] = 0.0f;
                             }
-                            a.route.keys[slot] = (e0 & M) | ((e1 & M) << 16);
+                            const RunInfo ri = row_runs(k0, k1, col);
+                            row_run_sums<2 * C::F>(v, ri.last, col);
+                            if (part && ri.head) {
+                                const int bkt = a.route.bucket_off[l] + (int)(e0 >> a.route.k);
+                                const uint32_t slot = atomicAdd(&cursor[bkt], 1u);
+                                if (slot < cursor_end[bkt]) {
+                                    float* dst = a.route.vals + (size_t)slot * (2 * C::F);
+                                    if constexpr (C::F == 2) {
+                                        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                                    } else {
+#pragma unroll
+                                        for (int j = 0; j < 2 * C::F; ++j) dst[j] = v[j];
+                                    }
+                                    a.route.keys[slot] = (e0 & M) | ((e1 & M) << 16);
+                                } else {                    // cannot happen when the counts match
+#pragma unroll
+                                    for (int j = 0; j < C::F; ++j) {
+                                        unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
+                                        unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
+                                    }
+                                }
+                            }
                         }
                     } else {
 #pragma unroll
@@ -486,10 +515,10 @@ bool train_supported(const GridHost& g, const NetShape& s) {
 // Workspace layout (each part 256-byte aligned):
 //   [G][n_w] partial weight gradients | [G] partial losses |
 //   routed scatter: [nb][G] offsets | [nb] totals | [nb+1] bases | [nb+1] chunk bases |
-//                   [R][2F] values | [R] keys
+//                   [R / chunk + nb] chunk buckets | [R][2F] values | [R] keys
 // with R = batch * n_levels * 4 records (one per corner x-pair).
 struct WsLayout {
-    int64_t w, loss, offsets, totals, base, chunk_base, vals, keys, total;
+    int64_t w, loss, offsets, totals, base, chunk_base, chunk_bucket, vals, keys, total;
 };
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -511,6 +540,8 @@ static WsLayout ws_layout(const GridHost& g, int64_t n_w, int64_t batch, int G, 
         o = align256(o + (int64_t)(rp.nb + 1) * 4);
         L.chunk_base = o;
         o = align256(o + (int64_t)(rp.nb + 1) * 4);
+        L.chunk_bucket = o;
+        o = align256(o + ((R + kRouteChunk - 1) / kRouteChunk + rp.nb) * 4);
         L.vals = o;
         o = align256(o + R * 2 * g.n_feat * 4);
         L.keys = o;
@@ -584,6 +615,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         r.totals = reinterpret_cast<uint32_t*>(ws + wl.totals);
         r.base = reinterpret_cast<uint32_t*>(ws + wl.base);
         r.chunk_base = reinterpret_cast<uint32_t*>(ws + wl.chunk_base);
+        r.chunk_bucket = reinterpret_cast<uint32_t*>(ws + wl.chunk_bucket);
         r.vals = reinterpret_cast<float*>(ws + wl.vals);
         r.keys = reinterpret_cast<uint32_t*>(ws + wl.keys);
         err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
@@ -591,7 +623,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         if (err != hipSuccess) return err;
     }
     err = hipErrorNotSupported;
-    const size_t cursor_bytes = rp.ok ? (size_t)rp.nb * 4 : 0;
+    const size_t cursor_bytes = rp.ok ? (size_t)rp.nb * 8 : 0;
     dispatch_config(gh.n_feat, s, [&]<class C>() {
         if constexpr (train_built<C>()) {
             hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM + cursor_bytes, st, a);
