@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=262144, help="pixels of the oracle's timed sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=256,
                     help="size of a plain device copy run after timing (counter calibration); 0 = none")
+    ap.add_argument("--loop", type=int, default=0,
+                    help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
+                         "moving) and print its per-frame report")
+    ap.add_argument("--loop-eval", type=int, default=65536, help="pixels of the loop's fixed evaluation subset")
     return ap.parse_args()
 
 
@@ -102,6 +106,91 @@ def cpu_baseline(wl, scene, params, sample_pix: int):
             "seconds": round(t3 - t0, 2), "ms_per_frame": frame_s * 1e3}
 
 
+def unshadowed(pos, nrm, lights):
+    """f[n][m] of the Lambertian point-light weight, FP32 (reporting only)."""
+    import torch
+    d = lights[None, :, :3] - pos[:, None, :]
+    d2 = torch.clamp((d * d).sum(-1), min=1e-6)
+    nd = torch.clamp((nrm[:, None, :] * d).sum(-1), min=0.0)
+    return lights[None, :, 3] * nd / (d2 * torch.sqrt(d2))
+
+
+def estimator_stats(f, V, v, floor):
+    """Exact per-pixel moments of the one-sample light estimator sum_i f_i V_i (FP32, reporting only).
+
+    Sampling p_i proportional to f_i (no cache) or to f_i max(v_i, floor) (cache):
+    Var = sum_i (f_i V_i)^2 / p_i - mu^2, and the probability of picking an occluded light."""
+    import torch
+    out = {}
+    mu = (f * V).sum(1)
+    for name, w in (("no_cache", f), ("cache", f * torch.clamp(v, min=floor))):
+        W = w.sum(1, keepdim=True)
+        ok = W[:, 0] > 0
+        p = torch.where(W > 0, w / torch.where(W > 0, W, torch.ones_like(W)), torch.zeros_like(w))
+        term = torch.where(p > 0, (f * V) ** 2 / torch.where(p > 0, p, torch.ones_like(p)), torch.zeros_like(p))
+        var = term.sum(1) - mu ** 2
+        out[name] = {"var": float(var[ok].mean()), "p_occluded": float((p * (V == 0)).sum(1)[ok].mean())}
+    return out
+
+
+def run_loop(args, wl, cache, scene, tens, dev):
+    """The frame loop: light 0 moves on a circle; each frame is one replay of a recorded HIP graph."""
+    import numpy as np
+    import torch
+
+    from paper_2506_05930_amd import api
+    from paper_2506_05930_amd.cache import FrameGraph
+    from workloads import moving_light_table
+
+    pos_unit, pos, nrm, lights, spheres = tens
+    n_frames = args.loop
+    table = torch.as_tensor(moving_light_table(scene["lights"], wl.frames or 60)).to(dev)
+    fg = None
+
+    def pre(stream):
+        idx = fg.ctr[0:1].long() % table.shape[0]
+        lights[0:1].copy_(table.index_select(0, idx))
+
+    fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch, pre=pre)
+    fg.capture()
+    n_pix = pos_unit.shape[0]
+    sub = torch.as_tensor(np.random.default_rng(3).choice(n_pix, size=min(args.loop_eval, n_pix), replace=False)
+                          .astype(np.int32)).to(dev)
+    sub_pos_unit = pos_unit.index_select(0, sub.long()).contiguous()
+    vis_sub = torch.empty((sub.shape[0], wl.mlp.n_out), dtype=cache.vis_dtype, device=dev)
+    lab_sub = torch.empty((sub.shape[0], wl.mlp.n_out), dtype=torch.uint8, device=dev)
+    frames = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):       # untimed frames to settle clocks; they also train
+        fg.replay()
+    torch.cuda.synchronize()
+    for f in range(n_frames):
+        e0.record()
+        fg.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        # evaluation on the fixed subset with this frame's lights (untimed)
+        cache.infer(sub_pos_unit, vis_sub)
+        api.nvc_shadow_labels(pos, sub, lights, spheres, lab_sub)
+        v = vis_sub.float()
+        y = lab_sub.float()
+        vc = torch.clamp(v, 1e-6, 1 - 1e-6)
+        rec = {"frame": int(fg.ctr[0].item()) - 1, "ms": round(ms, 4), "loss": round(float(cache.loss_buf.item()), 6),
+               "vis_mae": round(float((v - y).abs().mean()), 6),
+               "vis_bce": round(float(-(y * torch.log(vc) + (1 - y) * torch.log(1 - vc)).mean()), 6)}
+        fsub = unshadowed(pos.index_select(0, sub.long()), nrm.index_select(0, sub.long()), lights)
+        st = estimator_stats(fsub, y, v, cache.vis_floor)
+        rec["var_ratio_cache_vs_none"] = round(st["cache"]["var"] / st["no_cache"]["var"], 5)
+        rec["p_occluded"] = {k: round(st[k]["p_occluded"], 5) for k in st}
+        frames.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    ms = [r["ms"] for r in frames]
+    return {"workload": "loop_60f", "frames": n_frames, "warmup_frames": args.warmup, "graph": True,
+            "ms_per_frame_mean": float(np.mean(ms)), "ms_per_frame_median": float(np.median(ms)),
+            "per_frame": frames}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -116,6 +205,8 @@ def main():
     from workloads import box_scene, get_workload, init_params
 
     over = {"mlp_dtype": args.dtype} if args.dtype else {}
+    if args.loop and args.workload == "train_1080p":
+        args.workload = "loop_60f"
     wl = get_workload(args.workload, **over)
     dev = torch.device("cuda:0")
     scene = box_scene(wl.scene_seed, wl.width, wl.height, wl.n_boxes, wl.n_lights, wl.n_spheres)
@@ -137,6 +228,9 @@ def main():
     labels = torch.empty((B, wl.mlp.n_out), dtype=torch.uint8, device=dev)
     pix_ws = cache.pixel_workspace(n_pix)
     stream = torch.cuda.current_stream()
+    if args.loop:
+        print(json.dumps(run_loop(args, wl, cache, scene, (pos_unit, pos, nrm, lights, spheres), dev)))
+        return
 
     def step(frame, ev=None):
         def mark(i):

@@ -123,6 +123,19 @@ int nvc_encode(const nvc_grid* grid, const float* table, const float* pos, int64
 int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
               const float* pos, int64_t n, void* vis, int32_t vis_dtype, void* stream);
 
+/* Per-frame counters in DEVICE memory, for frames recorded once into a HIP
+ * graph and replayed: nvc_sample_wrs and nvc_select_pixels given a non-NULL
+ * `ctr` take the frame number from ctr->frame, and nvc_adam takes its step
+ * from ctr->step, when they run on the stream (the value arguments are then
+ * ignored).  nvc_counters_advance increments both on the stream. */
+typedef struct nvc_counters {
+    uint32_t frame;
+    int32_t step;             /* Adam step, >= 1 */
+} nvc_counters;
+
+/* ctr->frame += 1 and ctr->step += 1, enqueued on `stream`. */
+int nvc_counters_advance(nvc_counters* ctr, void* stream);
+
 /* Light selection by weighted reservoir sampling (Sec. 1, Sec. 3.1) and
  * neural direct illumination (Sec. 3.2).
  * vis: [n][m] in vis_dtype; pos: float32 [n][3] in scene units; nrm:
@@ -139,10 +152,11 @@ int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, cons
  * (seed lo32, seed hi32).  With C_i the sequential FP32 running sum of w in
  * light order and W = C_{m-1}: idx = the first i with C_i > u * W.
  * Outputs (float32 / int32 [n]): idx (-1 when W = 0), pmf = w_idx / W (0 when
- * W = 0), wsum = W, and, if di != NULL, di = sum_i v_i f_i / pi (raw v). */
+ * W = 0), wsum = W, and, if di != NULL, di = sum_i v_i f_i / pi (raw v).
+ * ctr (device, or NULL): if given, frame = ctr->frame at run time. */
 int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m,
                    const float* pos, const float* nrm, const float* lights, float vis_floor,
-                   uint64_t seed, uint32_t frame,
+                   uint64_t seed, uint32_t frame, const nvc_counters* ctr,
                    int32_t* idx, float* pmf, float* wsum, float* di, void* stream);
 
 /* Host only.  Workspace bytes nvc_select_pixels needs for an image of n_pix pixels. */
@@ -157,8 +171,9 @@ int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix);
  * nvc_train_step run faster on such batches; the training step sums over
  * the batch, so the order does not change it).  Deterministic.
  * workspace: nvc_select_pixels_workspace_bytes(n_pix) bytes of device memory.
+ * ctr (device, or NULL): if given, frame = ctr->frame at run time.
  * 1 <= n_pix < 2^31, 0 <= batch < 2^31. */
-int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch,
+int nvc_select_pixels(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
                       int32_t* pix, void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Shadow-ray labels (Sec. 3.4: one shadow ray from each training point to
@@ -210,9 +225,12 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
 /* One Adam step (Sec. 3.4; Kingma & Ba) over `count` FP32 parameters, dense:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
  *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)
- * step >= 1 counts from 1.  If zero_grad != 0, g is set to 0 afterwards
- * (the next nvc_train_step then accumulates into a clean buffer). */
-int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step,
+ * step >= 1 counts from 1 (with ctr: ctr->step at run time, values below 1
+ * taken as 1).  The bias corrections are computed on the device in FP32:
+ * b^step by repeated squaring, then a correctly rounded division and square
+ * root.  If zero_grad != 0, g is set to 0 afterwards (the next
+ * nvc_train_step then accumulates into a clean buffer). */
+int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, const nvc_counters* ctr,
              float lr, float beta1, float beta2, float eps, int32_t zero_grad, void* stream);
 
 #ifdef __cplusplus

@@ -27,7 +27,7 @@ EXPORTS = [
     "nvc_version", "nvc_status_string", "nvc_grid_levels", "nvc_mlp_param_count", "nvc_mlp_packed_bytes",
     "nvc_pack_mlp", "nvc_encode", "nvc_infer", "nvc_sample_wrs", "nvc_select_pixels_workspace_bytes",
     "nvc_select_pixels", "nvc_shadow_labels",
-    "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam",
+    "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
 ]
 
 
@@ -58,17 +58,19 @@ _SIGS = {
     "nvc_infer": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                             c_int32, c_void_p]),
     "nvc_sample_wrs": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_float,
-                                 c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+                                 c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nvc_select_pixels_workspace_bytes": (c_int64, [c_int64]),
-    "nvc_select_pixels": (c_int32, [c_uint64, c_uint32, c_int64, c_int64, c_void_p, c_void_p, c_int64, c_void_p]),
+    "nvc_select_pixels": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_int64,
+                                    c_void_p]),
     "nvc_shadow_labels": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32, c_void_p,
                                     c_void_p]),
     "nvc_train_workspace_bytes": (c_int64, [POINTER(NvcGrid), POINTER(NvcMlp), c_int64]),
     "nvc_train_step": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                  c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int64, c_void_p]),
-    "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_float, c_float, c_float,
-                           c_float, c_int32, c_void_p]),
+    "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_float, c_float,
+                           c_float, c_float, c_int32, c_void_p]),
+    "nvc_counters_advance": (c_int32, [c_void_p, c_void_p]),
 }
 
 _lib = None

@@ -120,9 +120,23 @@ def nvc_infer(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Ten
                                                   _DT_CODE[vis.dtype], _stream(stream)))
 
 
+def _counters(ctr):
+    """Device pointer of an nvc_counters block: an int32 tensor of 2 elements (frame, step), or None."""
+    return _ptr(ctr, "ctr", torch.int32, (2,), optional=True)
+
+
+def new_counters(frame: int = 0, step: int = 1, device="cuda") -> torch.Tensor:
+    """Device counters {uint32 frame; int32 step} for nvc_sample_wrs / nvc_select_pixels / nvc_adam."""
+    return torch.tensor([frame, step], dtype=torch.int32, device=device)
+
+
+def nvc_counters_advance(ctr: torch.Tensor, stream=None) -> None:
+    _lib.check("nvc_counters_advance", _lib.load().nvc_counters_advance(_counters(ctr), _stream(stream)))
+
+
 def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, vis_floor: float, seed: int,
                    frame: int, idx: torch.Tensor, pmf: torch.Tensor, wsum: torch.Tensor, di=None,
-                   stream=None) -> None:
+                   stream=None, ctr=None) -> None:
     n, m = vis.shape
     pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16))
     pp = _ptr(pos, "pos", torch.float32, (n, 3))
@@ -134,8 +148,8 @@ def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tens
     pd = _ptr(di, "di", torch.float32, (n,), optional=True)
     _lib.check("nvc_sample_wrs", _lib.load().nvc_sample_wrs(pv, _DT_CODE[vis.dtype], n, m, pp, pn, pl,
                                                             float(vis_floor), int(seed) & (2 ** 64 - 1),
-                                                            int(frame) & 0xFFFFFFFF, pi, pm, pw, pd,
-                                                            _stream(stream)))
+                                                            int(frame) & 0xFFFFFFFF, _counters(ctr), pi, pm, pw,
+                                                            pd, _stream(stream)))
 
 
 def nvc_select_pixels_workspace_bytes(n_pix: int) -> int:
@@ -143,11 +157,11 @@ def nvc_select_pixels_workspace_bytes(n_pix: int) -> int:
 
 
 def nvc_select_pixels(seed: int, frame: int, n_pix: int, pix: torch.Tensor, workspace: torch.Tensor,
-                      stream=None) -> None:
+                      stream=None, ctr=None) -> None:
     pp = _ptr(pix, "pix", torch.int32)
     pw = _ptr(workspace, "workspace")
     _lib.check("nvc_select_pixels", _lib.load().nvc_select_pixels(int(seed) & (2 ** 64 - 1),
-                                                                  int(frame) & 0xFFFFFFFF, int(n_pix),
+                                                                  int(frame) & 0xFFFFFFFF, _counters(ctr), int(n_pix),
                                                                   pix.numel(), pp, pw,
                                                                   workspace.numel() * workspace.element_size(),
                                                                   _stream(stream)))
@@ -190,10 +204,10 @@ def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torc
 
 
 def nvc_adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
-             beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None) -> None:
+             beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None, ctr=None) -> None:
     n = p.numel()
     ptrs = [_ptr(t, name, torch.float32) for t, name in ((p, "p"), (g, "g"), (m, "m"), (v, "v"))]
     if any(t.numel() != n for t in (g, m, v)):
         raise ValueError("p, g, m, v must have the same number of elements")
-    _lib.check("nvc_adam", _lib.load().nvc_adam(*ptrs, n, int(step), float(lr), float(beta1), float(beta2),
+    _lib.check("nvc_adam", _lib.load().nvc_adam(*ptrs, n, int(step), _counters(ctr), float(lr), float(beta1), float(beta2),
                                                 float(eps), int(bool(zero_grad)), _stream(stream)))

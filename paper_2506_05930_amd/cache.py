@@ -12,6 +12,8 @@ training workspace) and strings the C-ABI calls together:
 torch is used for device memory and the stream only; every step runs in
 libnvc.so.  `NVCFunction` exposes inference to torch autograd with the
 library's own backward (the training kernel in upstream-gradient mode).
+`FrameGraph` records one whole frame into a HIP graph once and replays it;
+the frame number and the Adam step then come from device counters.
 """
 from __future__ import annotations
 
@@ -87,7 +89,7 @@ class NVCache:
         return enc
 
     def sample(self, vis, pos, nrm, lights, frame: int, out: dict | None = None, with_di: bool = True,
-               stream=None) -> dict:
+               stream=None, ctr=None) -> dict:
         n = vis.shape[0]
         if out is None:
             out = {"idx": torch.empty(n, dtype=torch.int32, device=self.device),
@@ -95,7 +97,7 @@ class NVCache:
                    "wsum": torch.empty(n, dtype=torch.float32, device=self.device),
                    "di": torch.empty(n, dtype=torch.float32, device=self.device) if with_di else None}
         api.nvc_sample_wrs(vis, pos, nrm, lights, self.vis_floor, self.seed, frame, out["idx"], out["pmf"],
-                           out["wsum"], out.get("di"), stream)
+                           out["wsum"], out.get("di"), stream, ctr=ctr)
         return out
 
     # ------------------------------------------------------------ training
@@ -109,38 +111,41 @@ class NVCache:
                            self.loss, grad_scale, self.g_table, self.g_w, self.loss_buf if labels is not None else None,
                            self.workspace, stream)
 
-    def adam(self, stream=None):
-        """One Adam step on table and weights (gradients cleared), then repack the weights."""
-        self.step += 1
-        api.nvc_adam(self.table, self.g_table, self.m_table, self.v_table, self.step, self.lr, self.beta1,
-                     self.beta2, self.eps, True, stream)
-        api.nvc_adam(self.w, self.g_w, self.m_w, self.v_w, self.step, self.lr, self.beta1, self.beta2, self.eps,
-                     True, stream)
+    def adam(self, stream=None, ctr=None):
+        """One Adam step on table and weights (gradients cleared), then repack the weights.
+
+        With device counters `ctr` the step is ctr[1] when the kernels run (the
+        host mirror `self.step` is then advanced by the caller)."""
+        if ctr is None:
+            self.step += 1
+        for p, g, m, v in ((self.table, self.g_table, self.m_table, self.v_table), (self.w, self.g_w, self.m_w, self.v_w)):
+            api.nvc_adam(p, g, m, v, self.step, self.lr, self.beta1, self.beta2, self.eps, True, stream, ctr=ctr)
         self.pack(stream)
 
     def train_step(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
-                   stream=None) -> dict:
+                   stream=None, ctr=None) -> dict:
         """Pick `batch` pixels, label them with shadow rays, one gradient pass and one Adam step."""
         if bufs is None:
             bufs = {"pix": torch.empty(batch, dtype=torch.int32, device=self.device),
                     "labels": torch.empty((batch, self.mlp.n_out), dtype=torch.uint8, device=self.device)}
         api.nvc_select_pixels(self.seed, frame, pos_unit.shape[0], bufs["pix"], self.pixel_workspace(pos_unit.shape[0]),
-                              stream)
+                              stream, ctr=ctr)
         api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
         self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
-        self.adam(stream)
+        self.adam(stream, ctr=ctr)
         return bufs
 
     def frame(self, pos_unit, pos_scene, nrm, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
-              stream=None) -> dict:
+              stream=None, ctr=None) -> dict:
         """Inference + WRS + neural DI on every pixel, then one training step."""
         if bufs is None:
             n = pos_unit.shape[0]
             bufs = {"vis": torch.empty((n, self.mlp.n_out), dtype=self.vis_dtype, device=self.device)}
         self.infer(pos_unit, bufs["vis"], stream=stream)
-        bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=stream)
+        bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=stream,
+                                     ctr=ctr)
         bufs["train"] = self.train_step(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
-                                        stream=stream)
+                                        stream=stream, ctr=ctr)
         return bufs
 
     # ------------------------------------------------------------ checkpoint
@@ -157,6 +162,73 @@ class NVCache:
         self.g_table.zero_()
         self.g_w.zero_()
         self.pack()
+
+
+class FrameGraph:
+    """One frame of the cache recorded once into a HIP graph and replayed.
+
+    The frame is `NVCache.frame` (inference, WRS + neural DI, training pixels,
+    shadow labels, gradients, Adam, repack) followed by a device-counter
+    increment; the frame number and the Adam step are read from the counters
+    `ctr` (int32 [2]) when the kernels run, so every replay is the next
+    frame.  `pre(stream)`, if given, is recorded first (e.g. scene animation
+    driven by `ctr`).  Every buffer is allocated before capture; the library
+    calls allocate nothing, issue no memset and never synchronise.
+    """
+
+    def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, pre=None,
+                 frame0: int = 0):
+        self.cache = cache
+        self.args = (pos_unit, pos_scene, nrm, lights, spheres)
+        self.batch = int(batch)
+        self.pre = pre
+        dev = cache.device
+        self.ctr = api.new_counters(frame0, cache.step + 1, device=dev)
+        n = pos_unit.shape[0]
+        self.bufs = {"vis": torch.empty((n, cache.mlp.n_out), dtype=cache.vis_dtype, device=dev),
+                     "sample": {"idx": torch.empty(n, dtype=torch.int32, device=dev),
+                                "pmf": torch.empty(n, dtype=torch.float32, device=dev),
+                                "wsum": torch.empty(n, dtype=torch.float32, device=dev),
+                                "di": torch.empty(n, dtype=torch.float32, device=dev)},
+                     "train": {"pix": torch.empty(self.batch, dtype=torch.int32, device=dev),
+                               "labels": torch.empty((self.batch, cache.mlp.n_out), dtype=torch.uint8, device=dev)}}
+        cache._ensure_workspace(self.batch)
+        cache.pixel_workspace(n)
+        self.graph = None
+
+    def _body(self, stream):
+        if self.pre is not None:
+            self.pre(stream)
+        self.cache.frame(*self.args, 0, self.batch, self.bufs, stream=stream, ctr=self.ctr)
+        api.nvc_counters_advance(self.ctr, stream)
+
+    def run_eager(self):
+        """The same frame without the graph (the counters advance the same way)."""
+        self._body(torch.cuda.current_stream())
+        self.cache.step += 1
+
+    def capture(self):
+        torch.cuda.synchronize()
+        saved = self.ctr.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):        # warm-up of the recorded torch work, then restore the state
+            if self.pre is not None:
+                self.pre(side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.ctr.copy_(saved)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+        self.cache.step += 1
 
 
 class NVCFunction(torch.autograd.Function):

@@ -3,7 +3,7 @@
 // one write of every array: 32 bytes per parameter).
 #include <hip/hip_runtime.h>
 
-#include "nvc_internal.hpp"
+#include "device_common.hpp"
 
 namespace nvc {
 
@@ -11,14 +11,29 @@ __device__ inline void adam_one(float& p, float& g, float& m, float& v, float st
                                 float b2, float eps) {
     m = b1 * m + (1.0f - b1) * g;
     v = b2 * v + (1.0f - b2) * (g * g);
-    const float denom = __fsqrt_rn(v) / bc2_sqrt + eps;
+    const float denom = sqrt_rn(v) / bc2_sqrt + eps;
     p = p - step_size * (m / denom);
 }
 
+// b^t for t >= 1 by repeated squaring, every product rounded to FP32.
+__device__ inline float pow_steps(float b, int t) {
+    float r = 1.0f;
+    while (t > 0) {
+        if (t & 1) r = r * b;
+        b = b * b;
+        t >>= 1;
+    }
+    return r;
+}
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
-                                                   float* __restrict__ v, int64_t count, float step_size,
-                                                   float bc2_sqrt, float b1, float b2, float eps, int zero_grad,
-                                                   int aligned) {
+                                                   float* __restrict__ v, int64_t count, int step,
+                                                   const int32_t* __restrict__ step_dev, float lr, float b1, float b2,
+                                                   float eps, int zero_grad, int aligned) {
+    int t = step_dev ? *step_dev : step;
+    if (t < 1) t = 1;
+    const float step_size = __fdiv_rn(lr, 1.0f - pow_steps(b1, t));
+    const float bc2_sqrt = sqrt_rn(1.0f - pow_steps(b2, t));
     const int64_t n4 = aligned ? count / 4 : 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
@@ -41,18 +56,30 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float*
     }
 }
 
+__global__ void counters_advance_kernel(uint32_t* frame_dev, int32_t* step_dev) {
+    if (threadIdx.x == 0) {
+        *frame_dev = *frame_dev + 1u;
+        *step_dev = *step_dev + 1;
+    }
+}
+
 int cu_count();
 
-hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, float step_size, float bc2_sqrt,
-                       float beta1, float beta2, float eps, int zero_grad, hipStream_t st) {
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
+                       float lr, float beta1, float beta2, float eps, int zero_grad, hipStream_t st) {
     const int64_t n4 = (count + 3) / 4;
     int64_t blocks = (n4 + 255) / 256;
     const int64_t cap = (int64_t)cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     const int aligned = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15u) == 0;
-    adam_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, count, step_size, bc2_sqrt, beta1, beta2, eps,
+    adam_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, count, step, step_dev, lr, beta1, beta2, eps,
                                                  zero_grad, aligned);
+    return hipGetLastError();
+}
+
+hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st) {
+    counters_advance_kernel<<<1, 64, 0, st>>>(frame_dev, step_dev);
     return hipGetLastError();
 }
 

@@ -152,15 +152,15 @@ int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, cons
 }
 
 int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m, const float* pos, const float* nrm,
-                   const float* lights, float vis_floor, uint64_t seed, uint32_t frame, int32_t* idx, float* pmf,
-                   float* wsum, float* di, void* stream) {
+                   const float* lights, float vis_floor, uint64_t seed, uint32_t frame, const nvc_counters* ctr,
+                   int32_t* idx, float* pmf, float* wsum, float* di, void* stream) {
     if (!valid_dtype(vis_dtype)) return NVC_ERR_DTYPE;
     if (n < 0 || m < 1 || m > 128) return NVC_ERR_SHAPE;
     if (!(vis_floor >= 0.0f) || !isfinite(vis_floor)) return NVC_ERR_SHAPE;
     if (n == 0) return NVC_OK;
     if (!vis || !pos || !lights || !idx || !pmf || !wsum) return NVC_ERR_NULL;
-    return hip_status(launch_wrs(vis, vis_dtype, n, m, pos, nrm, lights, vis_floor, seed, frame, idx, pmf, wsum, di,
-                                 (hipStream_t)stream));
+    return hip_status(launch_wrs(vis, vis_dtype, n, m, pos, nrm, lights, vis_floor, seed, frame,
+                                 ctr ? &ctr->frame : nullptr, idx, pmf, wsum, di, (hipStream_t)stream));
 }
 
 int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix) {
@@ -168,13 +168,14 @@ int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix) {
     return select_pixels_workspace_bytes(n_pix);
 }
 
-int nvc_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix, void* workspace,
-                      int64_t workspace_bytes, void* stream) {
+int nvc_select_pixels(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
+                      int32_t* pix, void* workspace, int64_t workspace_bytes, void* stream) {
     if (n_pix < 1 || n_pix >= ((int64_t)1 << 31) || batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
     if (batch == 0) return NVC_OK;
     if (!pix) return NVC_ERR_NULL;
     if (!workspace || workspace_bytes < select_pixels_workspace_bytes(n_pix)) return NVC_ERR_WORKSPACE;
-    return hip_status(launch_select_pixels(seed, frame, n_pix, batch, pix, workspace, (hipStream_t)stream));
+    return hip_status(launch_select_pixels(seed, frame, ctr ? &ctr->frame : nullptr, n_pix, batch, pix, workspace,
+                                           (hipStream_t)stream));
 }
 
 int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int32_t m,
@@ -219,20 +220,20 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                                    g_w, loss_out, workspace, (hipStream_t)stream));
 }
 
-int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, float lr, float beta1, float beta2,
-             float eps, int32_t zero_grad, void* stream) {
-    if (count < 0 || step < 1) return NVC_ERR_SHAPE;
+int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, const nvc_counters* ctr, float lr,
+             float beta1, float beta2, float eps, int32_t zero_grad, void* stream) {
+    if (count < 0 || (!ctr && step < 1)) return NVC_ERR_SHAPE;
     if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f)) return NVC_ERR_SHAPE;
     if (!(lr >= 0.0f) || !isfinite(lr) || !(eps >= 0.0f) || !isfinite(eps)) return NVC_ERR_SHAPE;
     if (count == 0) return NVC_OK;
     if (!p || !g || !m || !v) return NVC_ERR_NULL;
-    // Bias corrections in FP64 on the host: step size lr / (1 - b1^t), sqrt(1 - b2^t).
-    const double bc1 = 1.0 - pow((double)beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)beta2, (double)step);
-    const float step_size = (float)((double)lr / bc1);
-    const float bc2_sqrt = (float)sqrt(bc2);
-    return hip_status(launch_adam(p, g, m, v, count, step_size, bc2_sqrt, beta1, beta2, eps, zero_grad,
-                                  (hipStream_t)stream));
+    return hip_status(launch_adam(p, g, m, v, count, step, ctr ? &ctr->step : nullptr, lr, beta1, beta2, eps,
+                                  zero_grad, (hipStream_t)stream));
+}
+
+int nvc_counters_advance(nvc_counters* ctr, void* stream) {
+    if (!ctr) return NVC_ERR_NULL;
+    return hip_status(launch_counters_advance(&ctr->frame, &ctr->step, (hipStream_t)stream));
 }
 
 }  // extern "C"

@@ -27,11 +27,13 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p,
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void pixel_count_kernel(uint32_t k0, uint32_t k1, uint32_t frame, uint32_t n_pix,
+__global__ __launch_bounds__(256) void pixel_count_kernel(uint32_t k0, uint32_t k1, uint32_t frame,
+                                                          const uint32_t* __restrict__ frame_dev, uint32_t n_pix,
                                                           int64_t batch, uint32_t* __restrict__ counts) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    const uint32_t r0 = philox_first_word((uint32_t)b, (uint32_t)((uint64_t)b >> 32), frame, 1u, k0, k1);
+    const uint32_t fr = frame_dev ? *frame_dev : frame;
+    const uint32_t r0 = philox_first_word((uint32_t)b, (uint32_t)((uint64_t)b >> 32), fr, 1u, k0, k1);
     atomicAdd(&counts[__umulhi(r0, n_pix)], 1u);
 }
 
@@ -108,8 +110,8 @@ int64_t select_pixels_workspace_bytes(int64_t n_pix) {
     return (2 * n_pix + nsums) * 4 + 512;
 }
 
-hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix,
-                                void* workspace, hipStream_t st) {
+hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
+                                int64_t batch, int32_t* pix, void* workspace, hipStream_t st) {
     uint32_t* counts = reinterpret_cast<uint32_t*>(workspace);
     uint32_t* offs = counts + n_pix;
     uint32_t* sums = offs + n_pix;
@@ -117,7 +119,7 @@ hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, in
     const unsigned pb = (unsigned)((n_pix + 255) / 256);
     fill_u32_kernel<<<pb, 256, 0, st>>>(counts, n_pix, 0u);
     pixel_count_kernel<<<(unsigned)((batch + 255) / 256), 256, 0, st>>>((uint32_t)seed, (uint32_t)(seed >> 32), frame,
-                                                                       (uint32_t)n_pix, batch, counts);
+                                                                       frame_dev, (uint32_t)n_pix, batch, counts);
     pixel_scan_local_kernel<<<(unsigned)nsums, 1024, 0, st>>>(counts, n_pix, offs, sums);
     pixel_scan_sums_kernel<<<1, 1024, 0, st>>>(sums, (int)nsums);
     pixel_emit_kernel<<<pb, 256, 0, st>>>(counts, offs, sums, n_pix, pix);

@@ -59,11 +59,11 @@ hipError_t launch_infer(const GridHost& g, const NetShape& s, const PackPlan& pl
                         const void* packed, const float* pos, int64_t n, void* vis, int vis_dtype, hipStream_t st);
 bool infer_supported(const GridHost& g, const NetShape& s);
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
-                      const float* lights, float vis_floor, uint64_t seed, uint32_t frame, int32_t* idx,
-                      float* pmf, float* wsum, float* di, hipStream_t st);
+                      const float* lights, float vis_floor, uint64_t seed, uint32_t frame,
+                      const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st);
 int64_t select_pixels_workspace_bytes(int64_t n_pix);
-hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, int64_t n_pix, int64_t batch, int32_t* pix,
-                                void* workspace, hipStream_t st);
+hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
+                                int64_t batch, int32_t* pix, void* workspace, hipStream_t st);
 size_t labels_smem_bytes(int m, int n_spheres);
 hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
                          const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st);
@@ -73,7 +73,9 @@ hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& pl
                         const void* packed, const float* pos, const int32_t* pix, int64_t batch,
                         const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
                         float* g_w, float* loss_out, void* workspace, hipStream_t st);
-hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, float step_size, float bc2_sqrt,
-                       float beta1, float beta2, float eps, int zero_grad, hipStream_t st);
+hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
+                       float lr, float beta1, float beta2, float eps, int zero_grad, hipStream_t st);
+// frame += 1, step += 1 of the device counters {uint32 frame; int32 step}.
+hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st);
 
 }  // namespace nvc

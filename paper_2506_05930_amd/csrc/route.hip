@@ -41,9 +41,10 @@ RoutePlan make_route_plan(const GridHost& g) {
 
 // Counts the records each training block will emit, per bucket.  Block j owns
 // the same samples as training block j: b = it * P + t for it = j, j + G, ...
-// A wave holds 64 consecutive samples of one level; runs of equal corner
-// x-pairs within aligned groups of 16 samples count once, as the training
-// kernel merges them.
+// The block's 256 threads split into 256 / P groups of P consecutive samples,
+// group s taking levels s, s + 256 / P, ...; runs of equal corner x-pairs
+// within aligned groups of 16 samples count once, as the training kernel
+// merges them.
 template <int F>
 __global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r, const float* __restrict__ pos,
                                                          const int32_t* __restrict__ pix, int64_t batch, int P) {
@@ -52,30 +53,28 @@ __global__ __launch_bounds__(256) void route_count_kernel(GridDev g, RouteDev r,
     __syncthreads();
     const int64_t iters = (batch + P - 1) / P;
     const uint32_t M = (1u << r.k) - 1u;
-    const int per_half = blockDim.x / 2;                     // P = 128 samples, two level parities
-    const int t = threadIdx.x % per_half;
-    const int half = threadIdx.x / per_half;
+    const int split = blockDim.x / P;
+    const int t = threadIdx.x % P;
+    const int sub = threadIdx.x / P;
     const int col = threadIdx.x & 15;
     for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
-        for (int s0 = 0; s0 < P; s0 += per_half) {
-            const int64_t b = it * P + s0 + t;
-            const bool valid = b < batch;
-            const int64_t src = valid ? (pix ? (int64_t)pix[b] : b) : 0;
-            const float x = valid ? clamp_unit(pos[src * 3 + 0]) : 0.0f;
-            const float y = valid ? clamp_unit(pos[src * 3 + 1]) : 0.0f;
-            const float z = valid ? clamp_unit(pos[src * 3 + 2]) : 0.0f;
-            for (int l = half; l < g.n_levels; l += 2) {
-                Corners cr;
-                level_corners(g, l, x, y, z, cr);
-                const bool dense = (g.dense_mask >> l) & 1u;
+        const int64_t b = it * P + t;
+        const bool valid = b < batch;
+        const int64_t src = valid ? (pix ? (int64_t)pix[b] : b) : 0;
+        const float x = valid ? clamp_unit(pos[src * 3 + 0]) : 0.0f;
+        const float y = valid ? clamp_unit(pos[src * 3 + 1]) : 0.0f;
+        const float z = valid ? clamp_unit(pos[src * 3 + 2]) : 0.0f;
+        for (int l = sub; l < g.n_levels; l += split) {
+            Corners cr;
+            level_corners(g, l, x, y, z, cr);
+            const bool dense = (g.dense_mask >> l) & 1u;
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
-                    const bool part = valid && !(dense && (e0 & M) == M);
-                    const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)(threadIdx.x & 63);
-                    const RunInfo ri = row_runs(k0, k1, col);
-                    if (part && ri.head) atomicAdd(&hist[r.bucket_off[l] + (e0 >> r.k)], 1u);
-                }
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
+                const bool part = valid && !(dense && (e0 & M) == M);
+                const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)(threadIdx.x & 63);
+                const RunInfo ri = row_runs(k0, k1, col);
+                if (part && ri.head) atomicAdd(&hist[r.bucket_off[l] + (e0 >> r.k)], 1u);
             }
         }
     }
@@ -226,6 +225,7 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
 
 hipError_t launch_route_count(const GridHost& gh, const RouteDev& r, const float* pos, const int32_t* pix,
                               int64_t batch, int grid, int pts_per_iter, hipStream_t st) {
+    if (pts_per_iter < 64 || 256 % pts_per_iter != 0) return hipErrorInvalidValue;   // whole waves per group
     const GridDev g = grid_to_dev(gh);
     const size_t smem = (size_t)r.nb * 4;
     if (gh.n_feat == 1)

@@ -52,6 +52,19 @@ struct RouteDev {
 };
 
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Row shifts within the 16-lane rows of a wave (DPP): lane i reads lane i + D
+// (row_shl) or lane i - D (row_shr) of its own row; reads past the row's ends
+// return 0 and are masked by the callers.
+template <int D> __device__ inline uint32_t row_from_next(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + D, 0xF, 0xF, true);
+}
+template <int D> __device__ inline float row_from_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + D, 0xF, 0xF, true));
+}
+__device__ inline uint32_t row_from_prev1(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x110 + 1, 0xF, 0xF, true);
+}
+
 // Runs of equal keys among the 16 lanes of a row (lanes 16r .. 16r+15 hold 16
 // consecutive samples): `head` marks the first lane of a run, `last` the last.
 struct RunInfo {
@@ -60,8 +73,8 @@ struct RunInfo {
 };
 
 __device__ inline RunInfo row_runs(uint32_t k0, uint32_t k1, int col) {
-    const uint32_t p0 = __shfl_up(k0, 1, 16), p1 = __shfl_up(k1, 1, 16);
-    const uint32_t n0 = __shfl_down(k0, 1, 16), n1 = __shfl_down(k1, 1, 16);
+    const uint32_t p0 = row_from_prev1(k0), p1 = row_from_prev1(k1);
+    const uint32_t n0 = row_from_next<1>(k0), n1 = row_from_next<1>(k1);
     RunInfo r;
     r.head = col == 0 || p0 != k0 || p1 != k1;
     r.last = col == 15 || n0 != k0 || n1 != k1;
@@ -70,21 +83,26 @@ __device__ inline RunInfo row_runs(uint32_t k0, uint32_t k1, int col) {
 
 // Reverse segmented sum within the row: afterwards each lane holds the sum of
 // its own value and those of the later lanes of its run (the head: the run).
+template <int D, int NV>
+__device__ inline void row_run_step(float (&v)[NV], uint32_t& e, int col) {
+    float o[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) o[j] = row_from_next<D>(v[j]);
+    const uint32_t eo = col + D < 16 ? row_from_next<D>(e) : 1u;
+    if (!e) {                                  // e == 0 implies col + D < 16 for the lanes that add
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] += o[j];
+    }
+    e |= eo;
+}
+
 template <int NV>
 __device__ inline void row_run_sums(float (&v)[NV], bool last, int col) {
-    bool e = last;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-        float o[NV];
-#pragma unroll
-        for (int j = 0; j < NV; ++j) o[j] = __shfl_down(v[j], d, 16);
-        const bool eo = col + d < 16 ? (bool)__shfl_down((int)e, d, 16) : true;
-        if (!e && col + d < 16) {
-#pragma unroll
-            for (int j = 0; j < NV; ++j) v[j] += o[j];
-        }
-        e = e || eo;
-    }
+    uint32_t e = last ? 1u : 0u;
+    row_run_step<1>(v, e, col);
+    row_run_step<2>(v, e, col);
+    row_run_step<4>(v, e, col);
+    row_run_step<8>(v, e, col);
 }
 #endif
 

@@ -20,7 +20,8 @@ template <int MAXM, typename VT>
 __global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, int64_t n, int m,
                                                  const float* __restrict__ pos, const float* __restrict__ nrm,
                                                  const float* __restrict__ lights, float vis_floor, uint32_t k0,
-                                                 uint32_t k1, uint32_t frame, int32_t* __restrict__ idx_out,
+                                                 uint32_t k1, uint32_t frame, const uint32_t* __restrict__ frame_dev,
+                                                 int32_t* __restrict__ idx_out,
                                                  float* __restrict__ pmf_out, float* __restrict__ wsum_out,
                                                  float* __restrict__ di_out) {
     __shared__ float4 L[MAXM];
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, in
             di = fmaf(v, f, di);
         }
     }
-    const uint32_t r0 = philox_first_word((uint32_t)p, (uint32_t)((uint64_t)p >> 32), frame, 0u, k0, k1);
+    const uint32_t fr = frame_dev ? *frame_dev : frame;
+    const uint32_t r0 = philox_first_word((uint32_t)p, (uint32_t)((uint64_t)p >> 32), fr, 0u, k0, k1);
     const float u = (float)(r0 >> 8) * 0x1.0p-24f;
     const float t = u * W;
     int pick = -1, last_pos = -1;
@@ -91,33 +93,34 @@ __global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, in
 
 template <typename VT>
 static void run_wrs(const VT* vis, int64_t n, int m, const float* pos, const float* nrm, const float* lights,
-                    float vis_floor, uint32_t k0, uint32_t k1, uint32_t frame, int32_t* idx, float* pmf,
-                    float* wsum, float* di, hipStream_t st) {
+                    float vis_floor, uint32_t k0, uint32_t k1, uint32_t frame, const uint32_t* frame_dev,
+                    int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st) {
     const unsigned blocks = (unsigned)((n + 255) / 256);
+    auto go = [&](auto kernel) {
+        kernel<<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf,
+                                       wsum, di);
+    };
     if (m <= 8)
-        wrs_kernel<8, VT><<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf,
-                                                  wsum, di);
+        go(wrs_kernel<8, VT>);
     else if (m <= 32)
-        wrs_kernel<32, VT><<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf,
-                                                   wsum, di);
+        go(wrs_kernel<32, VT>);
     else if (m <= 64)
-        wrs_kernel<64, VT><<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf,
-                                                   wsum, di);
+        go(wrs_kernel<64, VT>);
     else
-        wrs_kernel<128, VT><<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx,
-                                                    pmf, wsum, di);
+        go(wrs_kernel<128, VT>);
 }
 
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
-                      const float* lights, float vis_floor, uint64_t seed, uint32_t frame, int32_t* idx,
-                      float* pmf, float* wsum, float* di, hipStream_t st) {
+                      const float* lights, float vis_floor, uint64_t seed, uint32_t frame,
+                      const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di,
+                      hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (vis_dtype == DT_F32)
-        run_wrs((const float*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf, wsum, di, st);
+        run_wrs((const float*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
     else if (vis_dtype == DT_F16)
-        run_wrs((const _Float16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf, wsum, di, st);
+        run_wrs((const _Float16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
     else
-        run_wrs((const __bf16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, idx, pmf, wsum, di, st);
+        run_wrs((const __bf16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
     return hipGetLastError();
 }
 

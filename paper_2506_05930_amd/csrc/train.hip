@@ -4,15 +4,17 @@
 // weight gradient across the block, and scatter the encoding gradient into
 // the hash table with FP32 atomics.
 //
-// Block = 4 waves; a wave handles 32 samples (two 16-point sub-tiles) per
-// iteration, a block 128.  For each layer k, from the output down:
-//   1. every wave writes its delta_k and the layer input h_k (both in the
-//      matrix-core dtype) to LDS as [neuron][sample];
+// Block = 4 waves, one 16-sample tile per wave and iteration (64 samples).
+// The forward pass keeps only the current layer in registers and writes every
+// layer input h_k (in the matrix-core dtype) to LDS as [neuron][sample].  For
+// each layer k, from the output down:
+//   1. every wave writes its delta_k to the LDS delta buffer;
 //   2. every wave computes delta_{k-1} = W_k^T delta_k * act'(h_k) in registers
-//      (the transposed weight fragments make it a plain matrix-core product);
+//      (the transposed weight fragments make it a plain matrix-core product;
+//      the mask reads the wave's own columns of h_k);
 //   3. after a barrier, each wave adds its share of the 16x16 tiles of
-//      dW_k = delta_k h_k^T over the block's 128 samples into accumulators
-//      that live for the whole kernel;
+//      dW_k = delta_k h_k^T over the block's samples into accumulators that
+//      live for the whole kernel;
 //   4. barrier.
 // At the end each block writes its partial dW to the workspace and a second
 // kernel reduces the partials (deterministic; no weight atomics).
@@ -38,8 +40,7 @@ __device__ inline void static_for(F&& f) {
 }
 
 constexpr int kTrainWaves = 4;
-constexpr int kTrainSub = 2;                              // 16-point sub-tiles per wave
-constexpr int kTrainPts = 16 * kTrainSub * kTrainWaves;   // samples per block iteration
+constexpr int kTrainPts = 16 * kTrainWaves;   // samples per block iteration: one 16-point tile per wave
 
 struct TrainArgs {
     GridDev g;
@@ -68,6 +69,10 @@ struct TrainArgs {
     RouteDev route;       // routed table scatter (route.enabled == 0: direct atomics)
 };
 
+// LDS of one block, in the matrix-core dtype, [neuron][sample] with row stride
+// SD: the inputs h_0 .. h_{NL-1} of every layer (written by the forward pass,
+// read by the backward pass for the activation masks and the weight
+// gradients), then one delta buffer.
 template <class C>
 struct TrainShape {
     static constexpr int DT = C::DT;
@@ -76,7 +81,6 @@ struct TrainShape {
     static constexpr int NOUTB_K = (C::NOUTB + PADB - 1) / PADB * PADB;
     __host__ __device__ static constexpr int nbi(int k) { return k == 0 ? C::NINB : C::WB; }
     __host__ __device__ static constexpr int nbo(int k) { return k == NL - 1 ? C::NOUTB : C::WB; }
-    __host__ __device__ static constexpr int nbo_k(int k) { return k == NL - 1 ? NOUTB_K : C::WB; }
     __host__ __device__ static constexpr int tiles(int k) { return nbi(k) * nbo(k); }
     __host__ __device__ static constexpr int owned(int k) { return (tiles(k) + kTrainWaves - 1) / kTrainWaves; }
     __host__ __device__ static constexpr int acc_off(int k) {
@@ -84,92 +88,74 @@ struct TrainShape {
         for (int j = 0; j < k; ++j) o += owned(j);
         return o;
     }
+    __host__ __device__ static constexpr int hrow(int k) { return k == 0 ? 0 : 16 * C::NINB + 16 * C::WB * (k - 1); }
     static constexpr int ACC = acc_off(NL);
+    static constexpr int RH = hrow(NL);
     static constexpr int RD = 16 * (C::WB > NOUTB_K ? C::WB : NOUTB_K);
-    static constexpr int RH = 16 * (C::WB > C::NINB ? C::WB : C::NINB);
     static constexpr int PAD = DT == DT_F32 ? 4 : 8;
     static constexpr int SD = kTrainPts + PAD;              // row stride (elements)
     static constexpr int ELEM = DT == DT_F32 ? 4 : 2;
-    static constexpr size_t SMEM = (size_t)(RD + RH) * SD * ELEM;
-    static constexpr int KCMAX = kchunks<DT>(C::WB > C::NINB ? (C::WB > NOUTB_K ? C::WB : NOUTB_K)
-                                                             : (C::NINB > NOUTB_K ? C::NINB : NOUTB_K));
+    static constexpr size_t SMEM = (size_t)(RH + RD) * SD * ELEM;
 };
 
-// Shapes whose weight-gradient accumulators fit the register budget (at most
-// 16 owned 16x16 tiles per wave) get a training kernel.
+// Shapes whose weight-gradient accumulators fit the register file (at most 56
+// owned 16x16 tiles per wave: the 128-wide network, one wave per SIMD) and
+// whose activations fit the LDS get a training kernel.  The routed scatter's
+// cursors take 4 bytes per bucket on top; when they do not fit in the 160 KiB
+// of LDS the table gradient goes through direct atomics.
 template <class C> constexpr bool train_built() {
-    return TrainShape<C>::ACC <= 16 && TrainShape<C>::SMEM <= 96 * 1024;
+    return TrainShape<C>::ACC <= 56 && TrainShape<C>::SMEM <= 150 * 1024;
 }
 
 // delta_{k-1} (or d_enc) = W^T delta, with W^T fragments (rows = input neurons, K = output neurons).
 template <int DT, int NBK, int NBI>
-__device__ inline void back_layer(const typename Mma<DT>::elem* WT, int lane, const float (&d)[kTrainSub][NBK][4],
-                                  float (&out)[kTrainSub][NBI][4]) {
+__device__ inline void back_layer(const typename Mma<DT>::elem* WT, int lane, const float (&d)[NBK][4],
+                                  float (&out)[NBI][4]) {
     using M = Mma<DT>;
     constexpr int KC = kchunks<DT>(NBK);
 #pragma unroll
     for (int ib = 0; ib < NBI; ++ib) {
-        float4_t acc[kTrainSub];
+        float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < kTrainSub; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < KC; ++kc) acc = M::mma(load_frag<DT>(WT, ib, kc, KC, lane), make_frag<DT, NBK>(d, kc), acc);
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const typename M::frag a = load_frag<DT>(WT, ib, kc, KC, lane);
-#pragma unroll
-            for (int s = 0; s < kTrainSub; ++s) acc[s] = M::mma(a, make_frag<DT, NBK>(d[s], kc), acc[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < kTrainSub; ++s)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) out[s][ib][i] = acc[s][i];
+        for (int i = 0; i < 4; ++i) out[ib][i] = acc[i];
     }
 }
 
 template <int DT, int NBI, int NBO>
-__device__ inline void fwd_layer(const typename Mma<DT>::elem* W, int lane, const float (&in)[kTrainSub][NBI][4],
-                                 float (&out)[kTrainSub][NBO][4]) {
+__device__ inline void fwd_layer(const typename Mma<DT>::elem* W, int lane, const float (&in)[NBI][4],
+                                 float (&out)[NBO][4]) {
     using M = Mma<DT>;
     constexpr int KC = kchunks<DT>(NBI);
 #pragma unroll
     for (int ob = 0; ob < NBO; ++ob) {
-        float4_t acc[kTrainSub];
+        float4_t acc = float4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < kTrainSub; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < KC; ++kc) acc = M::mma(load_frag<DT>(W, ob, kc, KC, lane), make_frag<DT, NBI>(in, kc), acc);
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-            const typename M::frag a = load_frag<DT>(W, ob, kc, KC, lane);
-#pragma unroll
-            for (int s = 0; s < kTrainSub; ++s) acc[s] = M::mma(a, make_frag<DT, NBI>(in[s], kc), acc[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < kTrainSub; ++s)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) out[s][ob][i] = acc[s][i];
+        for (int i = 0; i < 4; ++i) out[ob][i] = acc[i];
     }
 }
 
-// Round a register activation array to the matrix-core dtype (what the MFMA
-// consumed), so staging and masks see the same values as the products.
+// Round a register tile to the matrix-core dtype (what the MFMA consumed), so
+// staging and masks see the same values as the products.
 template <int DT, int NB>
-__device__ inline void round_to_dtype(float (&a)[kTrainSub][NB][4]) {
+__device__ inline void round_to_dtype(float (&a)[NB][4]) {
 #pragma unroll
-    for (int s = 0; s < kTrainSub; ++s)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[s][b][i] = (float)Mma<DT>::cvt(a[s][b][i]);
+        for (int i = 0; i < 4; ++i) a[b][i] = (float)Mma<DT>::cvt(a[b][i]);
 }
 
-template <int DT, int NB>
-__device__ inline void stage(typename Mma<DT>::elem* buf, int SD, int wave, int lane, const float (&a)[kTrainSub][NB][4]) {
+// The wave's 16 columns of a [neuron][sample] LDS region.
+template <int DT, int NB, int SD>
+__device__ inline void stage(typename Mma<DT>::elem* buf, int wave, int lane, const float (&a)[NB][4]) {
     const int grp = lane >> 4, col = lane & 15;
 #pragma unroll
-    for (int s = 0; s < kTrainSub; ++s)
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                buf[(16 * b + 4 * grp + i) * SD + wave * 32 + s * 16 + col] = Mma<DT>::cvt(a[s][b][i]);
+        for (int i = 0; i < 4; ++i) buf[(16 * b + 4 * grp + i) * SD + wave * 16 + col] = Mma<DT>::cvt(a[b][i]);
 }
 
 // acc[j] += tile (ob, ib) of delta h^T over the block's samples, for the wave's owned tiles.
@@ -188,7 +174,7 @@ __device__ inline void accumulate_dw(const typename Mma<DT>::elem* D, const type
         const E* brow = H + (16 * ib + col) * SD;
         float4_t c = acc[OFF + j];
         if constexpr (DT == DT_F32) {
-#pragma unroll 8
+#pragma unroll
             for (int kc = 0; kc < kTrainPts / 4; ++kc) c = M::mma(arow[4 * kc + grp], brow[4 * kc + grp], c);
         } else {
 #pragma unroll
@@ -211,25 +197,21 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     constexpr int NL = TS::NL;
     constexpr int SD = TS::SD;
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
-    E* stD = reinterpret_cast<E*>(smem_raw);
-    E* stH = stD + TS::RD * SD;
+    E* stH = reinterpret_cast<E*>(smem_raw);
+    E* stD = stH + TS::RH * SD;
     __shared__ float red[kTrainWaves];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int grp = lane >> 4;
     const int col = lane & 15;
-    const E* packed = reinterpret_cast<const E*>(a.packed);
+    const E* packed0 = reinterpret_cast<const E*>(a.packed);
 
-    // Write cursors of the routed scatter: this block's range [cursor, cursor_end) in every bucket.
+    // Write cursors of the routed scatter: the next free record of this block in every bucket.
     uint32_t* cursor = reinterpret_cast<uint32_t*>(smem_raw + TS::SMEM);
-    uint32_t* cursor_end = cursor + (a.route.enabled ? a.route.nb : 0);
     if (a.route.enabled) {
-        for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x) {
-            const uint32_t* row = a.route.offsets + (int64_t)i * gridDim.x;
-            cursor[i] = a.route.base[i] + row[blockIdx.x];
-            cursor_end[i] = a.route.base[i] + (blockIdx.x + 1 < gridDim.x ? row[blockIdx.x + 1] : a.route.totals[i]);
-        }
+        for (int i = threadIdx.x; i < a.route.nb; i += blockDim.x)
+            cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)i * gridDim.x + blockIdx.x];
         __syncthreads();
     }
 
@@ -240,204 +222,199 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
 
     const int64_t iters = (a.batch + kTrainPts - 1) / kTrainPts;
     for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
-        // ---------------- forward (recomputed) ----------------
-        float x[kTrainSub][3];
-        bool valid[kTrainSub];
-        float h0[kTrainSub][C::NINB][4];
+        // ---------------- forward (recomputed); layer inputs go to LDS ----------------
+        // The weight fragments are loaded where they are used (from L1/L2) in
+        // every iteration: the empty asm stops the compiler from hoisting them
+        // out of the loop into registers, which would cost occupancy.
+        const E* packed = packed0;
+        asm volatile("" : "+s"(packed));
+        const int64_t b = it * kTrainPts + wave * 16 + col;
+        const bool valid = b < a.batch;
+        const int64_t bc = valid ? b : a.batch - 1;
+        const int64_t src = a.pix ? (int64_t)a.pix[bc] : bc;
+        const float x0 = clamp_unit(a.pos[src * 3 + 0]);
+        const float x1 = clamp_unit(a.pos[src * 3 + 1]);
+        const float x2 = clamp_unit(a.pos[src * 3 + 2]);
+        float z[TS::NOUTB_K][4];
+        {
+            float h0[C::NINB][4];
+            encode_lane<C::F, C::NINB>(a.table, a.g, grp, x0, x1, x2, h0);
+            round_to_dtype<DT, C::NINB>(h0);
+            stage<DT, C::NINB, SD>(stH, wave, lane, h0);
+            float h[C::WB][4];
+            fwd_layer<DT, C::NINB, C::WB>(packed + a.off_f[0], lane, h0, h);
+            static_for<1, NL>([&](auto kc_) {
+                constexpr int k = decltype(kc_)::value;      // h = pre-activation input of layer k
 #pragma unroll
-        for (int s = 0; s < kTrainSub; ++s) {
-            const int64_t b = it * kTrainPts + wave * 32 + s * 16 + col;
-            valid[s] = b < a.batch;
-            const int64_t bc = valid[s] ? b : a.batch - 1;
-            const int64_t src = a.pix ? (int64_t)a.pix[bc] : bc;
-            x[s][0] = clamp_unit(a.pos[src * 3 + 0]);
-            x[s][1] = clamp_unit(a.pos[src * 3 + 1]);
-            x[s][2] = clamp_unit(a.pos[src * 3 + 2]);
-            encode_lane<C::F, C::NINB>(a.table, a.g, grp, x[s][0], x[s][1], x[s][2], h0[s]);
-        }
-        round_to_dtype<DT, C::NINB>(h0);
-        float hh[C::NHID][kTrainSub][C::WB][4];        // inputs of layers 1..NHID (post-activation)
-        fwd_layer<DT, C::NINB, C::WB>(packed + a.off_f[0], lane, h0, hh[0]);
-        static_for<1, C::NHID + 1>([&](auto kc_) {
-            constexpr int k = decltype(kc_)::value;
-#pragma unroll
-            for (int s = 0; s < kTrainSub; ++s)
-#pragma unroll
-                for (int b = 0; b < C::WB; ++b)
+                for (int ob = 0; ob < C::WB; ++ob)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const float v = hh[k - 1][s][b][i];
-                        hh[k - 1][s][b][i] = v > 0.0f ? v : (a.act ? a.slope * v : 0.0f);
+                        const float v = h[ob][i];
+                        h[ob][i] = v > 0.0f ? v : (a.act ? a.slope * v : 0.0f);
                     }
-            round_to_dtype<DT, C::WB>(hh[k - 1]);
-            if constexpr (k < C::NHID) fwd_layer<DT, C::WB, C::WB>(packed + a.off_f[k], lane, hh[k - 1], hh[k]);
-        });
-        float z[kTrainSub][TS::NOUTB_K][4];
-        {
-            float zz[kTrainSub][C::NOUTB][4];
-            fwd_layer<DT, C::WB, C::NOUTB>(packed + a.off_f[NL - 1], lane, hh[C::NHID - 1], zz);
+                round_to_dtype<DT, C::WB>(h);
+                stage<DT, C::WB, SD>(stH + TS::hrow(k) * SD, wave, lane, h);
+                if constexpr (k < NL - 1) {
+                    float hn[C::WB][4];
+                    fwd_layer<DT, C::WB, C::WB>(packed + a.off_f[k], lane, h, hn);
 #pragma unroll
-            for (int s = 0; s < kTrainSub; ++s)
+                    for (int ob = 0; ob < C::WB; ++ob)
 #pragma unroll
-                for (int b = 0; b < TS::NOUTB_K; ++b)
+                        for (int i = 0; i < 4; ++i) h[ob][i] = hn[ob][i];
+                } else {
+                    float zz[C::NOUTB][4];
+                    fwd_layer<DT, C::WB, C::NOUTB>(packed + a.off_f[k], lane, h, zz);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) z[s][b][i] = b < C::NOUTB ? zz[s][b][i] : 0.0f;
+                    for (int ob = 0; ob < TS::NOUTB_K; ++ob)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) z[ob][i] = ob < C::NOUTB ? zz[ob][i] : 0.0f;
+                }
+            });
         }
 
         // ---------------- output gradient and loss ----------------
-        float d[kTrainSub][TS::NOUTB_K][4];
+        float d[TS::NOUTB_K][4];
 #pragma unroll
-        for (int s = 0; s < kTrainSub; ++s) {
-            const int64_t b = it * kTrainPts + wave * 32 + s * 16 + col;
+        for (int ob = 0; ob < TS::NOUTB_K; ++ob)
 #pragma unroll
-            for (int ob = 0; ob < TS::NOUTB_K; ++ob)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int li = 16 * ob + 4 * grp + i;
-                    float g = 0.0f;
-                    if (valid[s] && li < a.n_out) {
-                        const float zv = z[s][ob][i];
-                        const float v = sigmoidf_(zv);
-                        if (a.labels) {
-                            const float y = (float)a.labels[b * a.n_out + li];
-                            if (a.loss == 0) {
-                                g = v - y;
-                                loss_acc += fmaxf(zv, 0.0f) + log1pf(expf(-fabsf(zv))) - y * zv;
-                            } else {
-                                g = 2.0f * (v - y) * v * (1.0f - v);
-                                loss_acc += (v - y) * (v - y);
-                            }
+            for (int i = 0; i < 4; ++i) {
+                const int li = 16 * ob + 4 * grp + i;
+                float g = 0.0f;
+                if (valid && li < a.n_out) {
+                    const float zv = z[ob][i];
+                    const float v = sigmoidf_(zv);
+                    if (a.labels) {
+                        const float y = (float)a.labels[b * a.n_out + li];
+                        if (a.loss == 0) {
+                            g = v - y;
+                            loss_acc += fmaxf(zv, 0.0f) + log1pf(expf(-fabsf(zv))) - y * zv;
                         } else {
-                            g = a.dvis[b * a.n_out + li] * v * (1.0f - v);
+                            g = 2.0f * (v - y) * v * (1.0f - v);
+                            loss_acc += (v - y) * (v - y);
                         }
-                        g *= a.out_mul;
+                    } else {
+                        g = a.dvis[b * a.n_out + li] * v * (1.0f - v);
                     }
-                    d[s][ob][i] = g;
+                    g *= a.out_mul;
                 }
-        }
+                d[ob][i] = g;
+            }
 
         // ---------------- backward, output layer first ----------------
-        float dh[kTrainSub][C::WB][4];      // delta of the current hidden layer
-        float denc[kTrainSub][C::NINB][4];
+        float dh[C::WB][4];      // delta of the current hidden layer
+        float denc[C::NINB][4];
         static_for<0, NL>([&](auto kk_) {
             constexpr int k = NL - 1 - decltype(kk_)::value;
-            // 1. stage delta_k and the layer input h_k
+            // 1. stage delta_k
             if constexpr (k == NL - 1) {
                 round_to_dtype<DT, TS::NOUTB_K>(d);
-                stage<DT, TS::NOUTB_K>(stD, SD, wave, lane, d);
+                stage<DT, TS::NOUTB_K, SD>(stD, wave, lane, d);
             } else {
                 round_to_dtype<DT, C::WB>(dh);
-                stage<DT, C::WB>(stD, SD, wave, lane, dh);
+                stage<DT, C::WB, SD>(stD, wave, lane, dh);
             }
-            if constexpr (k == 0)
-                stage<DT, C::NINB>(stH, SD, wave, lane, h0);
-            else
-                stage<DT, C::WB>(stH, SD, wave, lane, hh[k - 1]);
-            // 2. propagate
+            // 2. propagate; the activation mask comes from the wave's own columns of h_k
             if constexpr (k > 0) {
-                float nd[kTrainSub][C::WB][4];
+                float nd[C::WB][4];
                 if constexpr (k == NL - 1)
                     back_layer<DT, TS::NOUTB_K, C::WB>(packed + a.off_b[k], lane, d, nd);
                 else
                     back_layer<DT, C::WB, C::WB>(packed + a.off_b[k], lane, dh, nd);
+                const E* hk = stH + TS::hrow(k) * SD + wave * 16 + col;
 #pragma unroll
-                for (int s = 0; s < kTrainSub; ++s)
+                for (int ob = 0; ob < C::WB; ++ob)
 #pragma unroll
-                    for (int b = 0; b < C::WB; ++b)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const float h = hh[k - 1][s][b][i];
-                            dh[s][b][i] = nd[s][b][i] * (h > 0.0f ? 1.0f : (a.act ? a.slope : 0.0f));
-                        }
+                    for (int i = 0; i < 4; ++i) {
+                        const float h = (float)hk[(16 * ob + 4 * grp + i) * SD];
+                        dh[ob][i] = nd[ob][i] * (h > 0.0f ? 1.0f : (a.act ? a.slope : 0.0f));
+                    }
             } else {
                 back_layer<DT, C::WB, C::NINB>(packed + a.off_b[0], lane, dh, denc);
             }
             __syncthreads();
             // 3. weight-gradient tiles over the block's samples
-            accumulate_dw<DT, TS::nbi(k), TS::nbo(k), TS::owned(k), TS::acc_off(k), TS::ACC, SD>(stD, stH, wave,
-                                                                                                  lane, acc);
+            accumulate_dw<DT, TS::nbi(k), TS::nbo(k), TS::owned(k), TS::acc_off(k), TS::ACC, SD>(
+                stD, stH + TS::hrow(k) * SD, wave, lane, acc);
             __syncthreads();
         });
 
         // ---------------- hash-table gradient ----------------
-        // Lane (grp, col) holds sample col of the sub-tile for the levels of
+        // Lane (grp, col) holds sample col of the wave's tile for the levels of
         // group grp, so each 16-lane row covers 16 consecutive samples of one
         // level.  With the routed scatter, equal corner x-pairs of consecutive
         // samples (frequent on coarse levels) are summed across the row first
         // and only the first lane of each run writes a record.
 #pragma unroll
-        for (int s = 0; s < kTrainSub; ++s) {
+        for (int bb = 0; bb < C::NINB; ++bb) {
 #pragma unroll
-            for (int b = 0; b < C::NINB; ++b) {
+            for (int q = 0; q < 4; q += C::F) {
+                const int feat = 16 * bb + 4 * grp + q;
+                const int l = feat / C::F;
+                const bool lvl_ok = l < a.g.n_levels;
+                if (!a.route.enabled && (!valid || !lvl_ok)) continue;
+                Corners cr;
+                level_corners(a.g, lvl_ok ? l : 0, x0, x1, x2, cr);
+                float* gl = a.g_table + (size_t)(lvl_ok ? l : 0) * a.g.T * C::F;
+                float dj[C::F];
 #pragma unroll
-                for (int q = 0; q < 4; q += C::F) {
-                    const int feat = 16 * b + 4 * grp + q;
-                    const int l = feat / C::F;
-                    const bool lvl_ok = l < a.g.n_levels;
-                    if (!a.route.enabled && (!valid[s] || !lvl_ok)) continue;
-                    Corners cr;
-                    level_corners(a.g, lvl_ok ? l : 0, x[s][0], x[s][1], x[s][2], cr);
-                    float* gl = a.g_table + (size_t)(lvl_ok ? l : 0) * a.g.T * C::F;
-                    float dj[C::F];
+                for (int j = 0; j < C::F; ++j) dj[j] = denc[bb][q + j] * a.final_mul;
+                if (a.route.enabled) {
+                    const uint32_t Mk = (1u << a.route.k) - 1u;
+                    const bool dense = lvl_ok && ((a.g.dense_mask >> l) & 1u);
 #pragma unroll
-                    for (int j = 0; j < C::F; ++j) dj[j] = denc[s][b][q + j] * a.final_mul;
-                    if (a.route.enabled) {
-                        const uint32_t M = (1u << a.route.k) - 1u;
-                        const bool dense = lvl_ok && ((a.g.dense_mask >> l) & 1u);
+                    for (int p = 0; p < 4; ++p) {
+                        const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
+                        float v[2 * C::F];
 #pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            const uint32_t e0 = cr.idx[2 * p], e1 = cr.idx[2 * p + 1];
-                            float v[2 * C::F];
+                        for (int j = 0; j < C::F; ++j) {
+                            v[j] = cr.w[2 * p] * dj[j];
+                            v[C::F + j] = cr.w[2 * p + 1] * dj[j];
+                        }
+                        const bool straddle = dense && (e0 & Mk) == Mk;   // pair spans two partitions
+                        if (valid && lvl_ok && straddle) {
 #pragma unroll
                             for (int j = 0; j < C::F; ++j) {
-                                v[j] = cr.w[2 * p] * dj[j];
-                                v[C::F + j] = cr.w[2 * p + 1] * dj[j];
+                                unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
+                                unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
                             }
-                            const bool straddle = dense && (e0 & M) == M;   // pair spans two partitions
-                            if (valid[s] && lvl_ok && straddle) {
+                        }
+                        const bool part = valid && lvl_ok && !straddle;
+                        // Keys of lanes that do not take part differ from every real key.
+                        const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)lane;
+                        if (!part) {
+#pragma unroll
+                            for (int j = 0; j < 2 * C::F; ++j) v[j] = 0.0f;
+                        }
+                        const RunInfo ri = row_runs(k0, k1, col);
+                        row_run_sums<2 * C::F>(v, ri.last, col);
+                        if (part && ri.head) {
+                            const int bkt = a.route.bucket_off[l] + (int)(e0 >> a.route.k);
+                            const uint32_t end = a.route.base[bkt + 1];
+                            const uint32_t slot = atomicAdd(&cursor[bkt], 1u);
+                            if (slot < end) {
+                                float* dst = a.route.vals + (size_t)slot * (2 * C::F);
+                                if constexpr (C::F == 2) {
+                                    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+                                } else {
+#pragma unroll
+                                    for (int j = 0; j < 2 * C::F; ++j) dst[j] = v[j];
+                                }
+                                a.route.keys[slot] = (e0 & Mk) | ((e1 & Mk) << 16);
+                            } else {                    // cannot happen when the counts match
 #pragma unroll
                                 for (int j = 0; j < C::F; ++j) {
                                     unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
                                     unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
                                 }
                             }
-                            const bool part = valid[s] && lvl_ok && !straddle;
-                            // Keys of lanes that do not take part differ from every real key.
-                            const uint32_t k0 = part ? e0 : 0xFFFFFFFFu, k1 = part ? e1 : (uint32_t)lane;
-                            if (!part) {
-#pragma unroll
-                                for (int j = 0; j < 2 * C::F; ++j) v[j] = 0.0f;
-                            }
-                            const RunInfo ri = row_runs(k0, k1, col);
-                            row_run_sums<2 * C::F>(v, ri.last, col);
-                            if (part && ri.head) {
-                                const int bkt = a.route.bucket_off[l] + (int)(e0 >> a.route.k);
-                                const uint32_t slot = atomicAdd(&cursor[bkt], 1u);
-                                if (slot < cursor_end[bkt]) {
-                                    float* dst = a.route.vals + (size_t)slot * (2 * C::F);
-                                    if constexpr (C::F == 2) {
-                                        *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
-                                    } else {
-#pragma unroll
-                                        for (int j = 0; j < 2 * C::F; ++j) dst[j] = v[j];
-                                    }
-                                    a.route.keys[slot] = (e0 & M) | ((e1 & M) << 16);
-                                } else {                    // cannot happen when the counts match
-#pragma unroll
-                                    for (int j = 0; j < C::F; ++j) {
-                                        unsafeAtomicAdd(gl + (size_t)e0 * C::F + j, v[j]);
-                                        unsafeAtomicAdd(gl + (size_t)e1 * C::F + j, v[C::F + j]);
-                                    }
-                                }
-                            }
                         }
-                    } else {
-#pragma unroll
-                        for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-                            for (int j = 0; j < C::F; ++j)
-                                unsafeAtomicAdd(gl + (size_t)cr.idx[kk] * C::F + j, cr.w[kk] * dj[j]);
                     }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+                        for (int j = 0; j < C::F; ++j)
+                            unsafeAtomicAdd(gl + (size_t)cr.idx[kk] * C::F + j, cr.w[kk] * dj[j]);
                 }
             }
         }
@@ -498,12 +475,39 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
     }
 }
 
-static int train_grid(int64_t batch) {
+// Persistent grid: as many blocks as stay resident (by the occupancy the
+// runtime reports for this kernel and LDS size; 2 per CU if it cannot say),
+// at most one per iteration.
+template <class C> static int train_blocks_per_cu(size_t smem) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, train_kernel<C>, 256, smem) != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        n = 2;
+    }
+    return n;
+}
+
+static int train_grid(const GridHost& gh, const NetShape& s, int64_t batch, size_t cursor_bytes) {
     const int64_t iters = (batch + kTrainPts - 1) / kTrainPts;
-    int64_t g = (int64_t)cu_count() * 2;
+    int per_cu = 2;
+    dispatch_config(gh.n_feat, s, [&]<class C>() {
+        if constexpr (train_built<C>()) per_cu = train_blocks_per_cu<C>(TrainShape<C>::SMEM + cursor_bytes);
+    });
+    int64_t g = (int64_t)cu_count() * per_cu;
     if (g > iters) g = iters;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+static size_t route_cursor_bytes(const RoutePlan& rp) { return rp.ok ? (size_t)rp.nb * 4 : 0; }
+
+// The routed scatter for this shape, if its cursors fit the LDS beside the activations.
+static RoutePlan train_route_plan(const GridHost& g, const NetShape& s) {
+    RoutePlan rp = make_route_plan(g);
+    size_t smem = 0;
+    dispatch_config(g.n_feat, s, [&]<class C>() { smem = TrainShape<C>::SMEM; });
+    if (rp.ok && smem + route_cursor_bytes(rp) > 160 * 1024) rp.ok = false;
+    return rp;
 }
 
 bool train_supported(const GridHost& g, const NetShape& s) {
@@ -556,7 +560,8 @@ static int64_t n_weights(const NetShape& s) {
 }
 
 int64_t train_workspace_bytes(const GridHost& g, const NetShape& s, int64_t batch) {
-    return ws_layout(g, n_weights(s), batch, train_grid(batch), make_route_plan(g)).total;
+    const RoutePlan rp = train_route_plan(g, s);
+    return ws_layout(g, n_weights(s), batch, train_grid(g, s, batch, route_cursor_bytes(rp)), rp).total;
 }
 
 hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
@@ -594,8 +599,9 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         a.final_mul = (float)(1.0 / gs);
     }
     a.g_table = g_table;
-    const int G = train_grid(batch);
-    const RoutePlan rp = make_route_plan(gh);
+    const RoutePlan rp = train_route_plan(gh, s);
+    const size_t cursor_bytes = route_cursor_bytes(rp);
+    const int G = train_grid(gh, s, batch, cursor_bytes);
     const WsLayout wl = ws_layout(gh, a.n_w, batch, G, rp);
     unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
     a.ws_w = reinterpret_cast<float*>(ws + wl.w);
@@ -623,7 +629,6 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         if (err != hipSuccess) return err;
     }
     err = hipErrorNotSupported;
-    const size_t cursor_bytes = rp.ok ? (size_t)rp.nb * 8 : 0;
     dispatch_config(gh.n_feat, s, [&]<class C>() {
         if constexpr (train_built<C>()) {
             hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM + cursor_bytes, st, a);

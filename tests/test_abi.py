@@ -28,7 +28,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) >= 14
+    assert len(names) >= 16
     out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (nvc_[a-z0-9_]+)", out))
     missing = [n for n in names if n not in exported]
@@ -97,26 +97,28 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_infer(gg, ctypes.byref(m(width=48)), P, P, P, 10, P, 1, N) == _lib.NVC_ERR_UNSUPPORTED
     assert lib.nvc_infer(gg, mm, None, P, P, 10, P, 1, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_infer(gg, mm, None, None, None, 0, None, 1, N) == 0
-    assert lib.nvc_sample_wrs(P, 1, 10, 0, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 129, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_NULL
-    assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, P, P, P, N, N) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 0, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 129, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_DTYPE
     ws = lib.nvc_select_pixels_workspace_bytes(100)
     assert ws >= 800
     assert lib.nvc_select_pixels_workspace_bytes(0) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_select_pixels(0, 0, 0, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_select_pixels(0, 0, 1 << 31, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_select_pixels(0, 0, 100, 10, None, P, ws, N) == _lib.NVC_ERR_NULL
-    assert lib.nvc_select_pixels(0, 0, 100, 10, P, P, ws - 1, N) == _lib.NVC_ERR_WORKSPACE
-    assert lib.nvc_select_pixels(0, 0, 100, 10, P, None, ws, N) == _lib.NVC_ERR_WORKSPACE
+    assert lib.nvc_select_pixels(0, 0, N, 0, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, N, 1 << 31, 10, P, P, ws, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels(0, 0, N, 100, 10, None, P, ws, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_select_pixels(0, 0, N, 100, 10, P, P, ws - 1, N) == _lib.NVC_ERR_WORKSPACE
+    assert lib.nvc_select_pixels(0, 0, N, 100, 10, P, None, ws, N) == _lib.NVC_ERR_WORKSPACE
     assert lib.nvc_shadow_labels(P, N, 10, P, 0, P, 1, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels(P, N, 10, P, 32, None, 4, P, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_shadow_labels(P, N, 10, P, 128, P, 4097, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels(P, N, -1, P, 32, P, 16, P, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(P, P, P, P, 10, 0, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(P, P, P, P, 10, 1, 1e-2, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(None, P, P, P, 10, 1, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_adam(P, P, P, P, 10, 0, N, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 1e-2, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(None, P, P, P, 10, 1, N, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_adam(P, P, P, P, 10, 0, P, 1e-2, 0.9, 1.5, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_counters_advance(None, N) == _lib.NVC_ERR_NULL
 
 
 def test_train_step_validation(lib):
@@ -133,10 +135,11 @@ def test_train_step_validation(lib):
     assert lib.nvc_train_step(gg, mm, P, P, P, N, 1 << 18, P, N, 0, 0.0, P, P, N, P, ws - 1, N) == \
         _lib.NVC_ERR_WORKSPACE
     assert lib.nvc_train_step(gg, mm, P, P, P, N, 64, P, N, 0, 0.0, P, P, N, None, ws, N) == _lib.NVC_ERR_WORKSPACE
-    # the 128-wide network has no training kernel yet
-    wide = ctypes.byref(m(width=128, n_out=128))
+    # the 128-wide network trains; a shape with no kernel is refused
     g20 = ctypes.byref(g(log2_T=20))
-    assert lib.nvc_train_workspace_bytes(g20, wide, 1024) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_train_workspace_bytes(g20, ctypes.byref(m(width=128, n_out=128)), 1024) > 0
+    assert lib.nvc_train_workspace_bytes(g20, ctypes.byref(m(width=128, n_out=128, n_hidden=2)), 1024) == \
+        _lib.NVC_ERR_UNSUPPORTED
 
 
 def test_python_binding_rejects_cpu_tensors():

@@ -238,7 +238,8 @@ def _rel_l2(a, b):
 
 
 GRAD_CASES = [("tiny", "f32", 1e-4, 1000), ("tiny", "f16", 3e-2, 1000), ("frame_1080p", "f32", 1e-4, 2085),
-              ("frame_1080p", "f16", 3e-2, 2085), ("frame_1080p", "bf16", 1e-1, 2085)]
+              ("frame_1080p", "f16", 3e-2, 2085), ("frame_1080p", "bf16", 1e-1, 2085),
+              ("sweep_4k", "f32", 1e-4, 700), ("sweep_4k", "f16", 3e-2, 700), ("sweep_4k", "bf16", 1e-1, 700)]
 
 
 @pytest.mark.parametrize("wl_name,dtype,tol,batch", GRAD_CASES)

@@ -13,9 +13,11 @@ from .scenes import (
     init_params,
     pos_to_unit,
     moving_light,
+    moving_light_table,
 )
 
 __all__ = [
     "GridCfg", "MlpCfg", "Workload", "WORKLOADS", "get_workload",
     "unit_cube_scene", "box_scene", "init_params", "pos_to_unit", "moving_light",
+    "moving_light_table",
 ]

@@ -213,6 +213,11 @@ def moving_light(lights: np.ndarray, frame: int, n_frames: int = 60, radius: flo
     return out
 
 
+def moving_light_table(lights: np.ndarray, n_frames: int = 60, radius: float = 3.0, center_xz=(5.0, 5.0)) -> np.ndarray:
+    """Row f = light 0 of `moving_light(lights, f, ...)`: float32 [n_frames][4]."""
+    return np.stack([moving_light(lights, f, n_frames, radius, center_xz)[0] for f in range(n_frames)]).astype(np.float32)
+
+
 def flatten_weights(weights) -> np.ndarray:
     """Concatenate per-layer [out][in] FP32 matrices into the flat master-weight buffer."""
     return np.concatenate([w.reshape(-1) for w in weights]).astype(np.float32)
