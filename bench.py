@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--workload", default="train_1080p")
     ap.add_argument("--dtype", default=None, help="override the MLP dtype (f32, f16, bf16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=262144, help="pixels of the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=655360, help="pixels of the oracle's timed sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=256,
                     help="size of a plain device copy run after timing (counter calibration); 0 = none")
     ap.add_argument("--loop", type=int, default=0,
@@ -80,7 +80,7 @@ def cpu_baseline(wl, scene, params, sample_pix: int):
 
     n_pix = scene["pos"].shape[0]
     sel = np.arange(sample_pix)
-    batch_s = max(1024, wl.train_batch // 4)
+    batch_s = max(1024, wl.train_batch // 2)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         vis = pipeline.infer(scene["pos_unit"][sel], params["table"], params["weights"], wl.grid.base_res,
@@ -104,6 +104,30 @@ def cpu_baseline(wl, scene, params, sample_pix: int):
                        f"Adam on {n_adam} params; FP64 NumPy, 1 thread, extrapolated linearly to one "
                        f"{n_pix}-pixel frame with a {wl.train_batch}-sample step"),
             "seconds": round(t3 - t0, 2), "ms_per_frame": frame_s * 1e3}
+
+
+def measured_traffic(stage, wl):
+    """HBM bytes per launch of the stage's kernel from the committed counter summary, if the kernel's
+    sources are still those the counters were taken on (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{stage}_1080p_traffic.txt")
+    if wl.name not in ("train_1080p", "frame_1080p") or wl.mlp.dtype != "f16" or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith((" ", "#")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv["kernel_sources"].split(","):
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != kv["kernel_sources_sha256"]:
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
 
 
 def unshadowed(pos, nrm, lights):
@@ -283,21 +307,25 @@ def main():
         torch.cuda.synchronize()
 
     alg = algorithmic(wl, n_pix, B)
-    dominant = max(stage_ms, key=stage_ms.get)
     rates = {}
     for s, d in alg.items():
         t = stage_ms[s] / 1e3
         rates[s] = {k: v / t for k, v in d.items()}
+    # Roofline of the dominant kernel.  infer, wrs and labels are one launch
+    # each, so their event times are those kernels' durations; the train and
+    # adam stages are several launches whose largest is shorter than infer's.
+    dominant = max(("infer", "wrs", "labels"), key=lambda k: stage_ms[k])
     if dominant == "labels":
         roof = {"bound": "alu", "achieved": rates["labels"]["ops"] / 1e12, "peak": PEAK_ALU_TOPS,
                 "unit": "Tops/s"}
-    elif dominant in ("infer", "wrs", "adam", "train"):
-        roof = {"bound": "hbm", "achieved": rates[dominant]["bytes"] / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     else:
         roof = {"bound": "hbm", "achieved": rates[dominant]["bytes"] / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = dominant
-    roof["traffic"] = None
+    roof["kernel"] = {"infer": "infer_kernel", "wrs": "wrs_kernel", "labels": "labels_kernel"}[dominant]
+    roof["avg_launch_ms"] = stage_ms[dominant]
+    hbm = measured_traffic(dominant, wl)
+    roof["traffic"] = None if hbm is None else hbm / (stage_ms[dominant] / 1e3) / 1e9
+    roof["traffic_bytes_per_launch"] = hbm
 
     q_infer_wrs = n_pix / ((stage_ms["infer"] + stage_ms["wrs"]) / 1e3)
     result = {

@@ -67,8 +67,10 @@ typedef struct nvc_grid {
 } nvc_grid;
 
 /* Visibility MLP (Sec. 3.3), host struct: n_in -> width (x n_hidden) -> n_out,
- * no biases, hidden activation `act` (NVC_ACT_LEAKY uses leaky_slope), sigmoid
- * output.  `dtype` is the precision of weights and activations fed to the
+ * no biases, hidden activation `act` (NVC_ACT_LEAKY uses leaky_slope, which
+ * must lie in [0, 1]), sigmoid output, evaluated from the FP32 accumulator as
+ * 1 / (1 + e) or e / (1 + e) with e = exp(-|z|) from the hardware exp2 and
+ * reciprocal (relative error a few 1e-7).  `dtype` is the precision of weights and activations fed to the
  * matrix cores (NVC_F32 uses FP32 matrix cores); accumulation is FP32.
  * n_in must equal n_levels * n_feat of the grid it is used with.
  * Master weights: float32, the layers' row-major [out][in] matrices

@@ -46,6 +46,7 @@ int check_mlp(const nvc_mlp* m, NetShape* out) {
     if (m->n_hidden + 1 > kMaxLayers) return NVC_ERR_UNSUPPORTED;
     if (m->n_out > 128 || m->n_in > 64 || m->width > 128) return NVC_ERR_UNSUPPORTED;
     if (m->act != NVC_ACT_RELU && m->act != NVC_ACT_LEAKY) return NVC_ERR_SHAPE;
+    if (m->act == NVC_ACT_LEAKY && !(m->leaky_slope >= 0.0f && m->leaky_slope <= 1.0f)) return NVC_ERR_SHAPE;
     NetShape s{};
     s.dtype = m->dtype;
     s.n_in = m->n_in;

@@ -255,11 +255,18 @@ __device__ inline float sqrt_rn(float x) {
     return s;
 }
 
-// Logistic function evaluated from the FP32 accumulator.
-__device__ inline float sigmoidf_(float z) {
-    if (z >= 0.0f) return 1.0f / (1.0f + expf(-z));
-    const float e = expf(z);
-    return e / (1.0f + e);
+// exp(-|z|) with the hardware base-2 exponential (within 1 ulp of exp2 of
+// the rounded product; 0 once it underflows).
+__device__ inline float exp_neg_abs(float z) { return __builtin_amdgcn_exp2f(-fabsf(z) * 1.44269504088896341f); }
+
+// Logistic function of the FP32 accumulator in the stable form, given
+// e = exp(-|z|): 1 / (1 + e) for z >= 0, e / (1 + e) otherwise, with the
+// hardware reciprocal (relative error a few 1e-7 for |z| < 16).
+__device__ inline float sigmoid_from(float z, float e) {
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    return z >= 0.0f ? r : e * r;
 }
+
+__device__ inline float sigmoidf_(float z) { return sigmoid_from(z, exp_neg_abs(z)); }
 
 }  // namespace nvc

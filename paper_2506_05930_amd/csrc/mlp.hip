@@ -116,15 +116,14 @@ __device__ inline void mlp_layer(const typename Mma<DT>::elem* W, int lane, cons
 }
 
 template <int NSUB, int NB>
-__device__ inline void activate(float (&a)[NSUB][NB][4], int act, float slope) {
+__device__ inline void activate(float (&a)[NSUB][NB][4], float slope) {
 #pragma unroll
     for (int s = 0; s < NSUB; ++s)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float x = a[s][b][i];
-                a[s][b][i] = x > 0.0f ? x : (act ? slope * x : 0.0f);
+                a[s][b][i] = fmaxf(a[s][b][i], slope * a[s][b][i]);   // ReLU (slope 0) or leaky, 0 <= slope <= 1
             }
 }
 
@@ -220,15 +219,15 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
         }
         float ha[NSUB][C::WB][4], hb[NSUB][C::WB][4];
         mlp_layer<DT, NSUB, C::NINB, C::WB>(wk[0], lane, h0, ha);
-        activate<NSUB, C::WB>(ha, a.act, a.slope);
+        activate<NSUB, C::WB>(ha, a.slope);
 #pragma unroll
         for (int k = 1; k < C::NHID; ++k) {
             if (k % 2 == 1) {
                 mlp_layer<DT, NSUB, C::WB, C::WB>(wk[k], lane, ha, hb);
-                activate<NSUB, C::WB>(hb, a.act, a.slope);
+                activate<NSUB, C::WB>(hb, a.slope);
             } else {
                 mlp_layer<DT, NSUB, C::WB, C::WB>(wk[k], lane, hb, ha);
-                activate<NSUB, C::WB>(ha, a.act, a.slope);
+                activate<NSUB, C::WB>(ha, a.slope);
             }
         }
         float z[NSUB][C::NOUTB][4];

@@ -14,7 +14,7 @@ RoutePlan make_route_plan(const GridHost& g) {
     const uint64_t T = 1ull << g.log2_T;
     for (int k = 12; k <= 14; ++k) {
         const uint64_t ps = 1ull << k;
-        if (ps * (uint64_t)g.n_feat * 4 > 128 * 1024) break;
+        if (ps * (uint64_t)g.n_feat * 8 > 128 * 1024) break;        // fixed-point partition in LDS
         bool ok = true;
         int nb = 0;
         for (int l = 0; l < g.n_levels && ok; ++l) {
@@ -160,14 +160,20 @@ __global__ __launch_bounds__(1024) void route_scan_kernel(RouteDev r) {
 }
 
 // One block per chunk of a bucket: sum the chunk's records into an LDS copy of
-// the partition, then add it to the gradient (plain stores if the bucket has a
-// single chunk, atomics otherwise; 16 lanes cover one 64-byte line).
+// the partition in 64-bit fixed point, then add it to the gradient (plain
+// stores if the bucket has a single chunk, atomics otherwise).
 template <int F>
 __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n_levels, uint32_t T,
-                                                              float* __restrict__ g_table) {
-    extern __shared__ float part[];
+                                                              float* __restrict__ g_table, int vec, int G) {
+    extern __shared__ unsigned long long part[];       // [2^k][F] fixed-point sums
+    __shared__ float red[16];
     const uint32_t c = blockIdx.x;
     if (c >= r.chunk_base[r.nb]) return;
+    // The step's scale, from the training blocks' record maxima (every block gets the same one).
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) m = fmaxf(m, r.rec_max[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     const int b = (int)r.chunk_bucket[c];
     int l = 0;
     while (l + 1 < n_levels && r.bucket_off[l + 1] <= b) ++l;
@@ -178,17 +184,23 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
     const bool shared = r.chunk_base[b + 1] - r.chunk_base[b] > 1;
     const uint32_t r0 = r.base[b] + q * (uint32_t)kRouteChunk;
     const uint32_t r1 = min(r.base[b + 1], r0 + (uint32_t)kRouteChunk);
-    for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0.0f;
+    for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0ull;
     __syncthreads();
-    // Four records per thread and step, all loads issued before the LDS adds.
-    constexpr int U = 4;
-    for (uint32_t i0 = r0 + threadIdx.x; i0 < r1; i0 += U * blockDim.x) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
+    const int S = route_fixed_shift(m);
+    const float scale = ldexpf(1.0f, S), inv_scale = ldexpf(1.0f, -S);
+    // Thread t adds records [t S', (t + 1) S') of the chunk, eight per step
+    // with all loads issued before the LDS adds.
+    constexpr int U = 8;
+    const uint32_t per = (r1 - r0 + blockDim.x - 1) / blockDim.x;
+    const uint32_t t0 = r0 + threadIdx.x * per;
+    for (uint32_t u0 = 0; u0 < per; u0 += U) {
         uint32_t key[U];
         float w[U][2 * F];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t i = i0 + u * blockDim.x;
-            const bool ok = i < r1;
+            const uint32_t i = t0 + u0 + u;
+            const bool ok = u0 + u < per && i < r1;
             key[u] = ok ? r.keys[i] : 0u;
             const float* v = r.vals + (size_t)(ok ? i : r0) * (2 * F);
             if constexpr (F == 2) {
@@ -208,18 +220,43 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
             const uint32_t lo0 = key[u] & 0xFFFFu, lo1 = key[u] >> 16;
 #pragma unroll
             for (int j = 0; j < F; ++j) {
-                atomicAdd(&part[lo0 * F + j], w[u][j]);
-                atomicAdd(&part[lo1 * F + j], w[u][F + j]);
+                atomicAdd(&part[lo0 * F + j], (unsigned long long)to_fixed(w[u][j], scale));
+                atomicAdd(&part[lo1 * F + j], (unsigned long long)to_fixed(w[u][F + j], scale));
             }
         }
     }
     __syncthreads();
+    // The partition's entries start at a multiple of 2^k (k >= 12), so the
+    // output is 16-byte aligned when g_table is (vec); the last partition of a
+    // dense level may end mid-vector and takes a scalar tail.
     float* out = g_table + ((size_t)l * T + pbase) * F;
+    const long long* sums = reinterpret_cast<const long long*>(part);
     if (shared) {
         for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x)
-            if (part[i] != 0.0f) unsafeAtomicAdd(out + i, part[i]);
+            if (sums[i] != 0) unsafeAtomicAdd(out + i, from_fixed(sums[i], inv_scale));
     } else {
-        for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x) out[i] += part[i];
+        // All loads of a thread's vectors first, then the adds and stores: one memory round trip.
+        const uint32_t nv = vec ? cnt * F / 4 : 0;
+        constexpr int V = 8;
+        for (uint32_t v0 = threadIdx.x; v0 < nv; v0 += V * blockDim.x) {
+            float4 o[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const uint32_t v = v0 + u * blockDim.x;
+                if (v < nv) o[u] = reinterpret_cast<const float4*>(out)[v];
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const uint32_t v = v0 + u * blockDim.x;
+                if (v < nv) {
+                    const long long* sv = sums + 4 * v;
+                    reinterpret_cast<float4*>(out)[v] =
+                        make_float4(o[u].x + from_fixed(sv[0], inv_scale), o[u].y + from_fixed(sv[1], inv_scale),
+                                    o[u].z + from_fixed(sv[2], inv_scale), o[u].w + from_fixed(sv[3], inv_scale));
+                }
+            }
+        }
+        for (uint32_t i = nv * 4 + threadIdx.x; i < cnt * F; i += blockDim.x) out[i] += from_fixed(sums[i], inv_scale);
     }
 }
 
@@ -246,18 +283,22 @@ hipError_t launch_route_prefix(const RouteDev& r, int grid, hipStream_t st) {
 }
 
 hipError_t launch_route_accumulate(const GridHost& gh, const RouteDev& r, float* g_table, int64_t max_records,
-                                   hipStream_t st) {
+                                   int train_blocks, hipStream_t st) {
     const uint32_t T = 1u << gh.log2_T;
-    const size_t smem = ((size_t)1 << r.k) * gh.n_feat * 4;
+    const size_t smem = ((size_t)1 << r.k) * gh.n_feat * 8;
     // Upper bound of the chunk count (the exact one is on the device): every
     // bucket has at most one partial chunk.
     const unsigned blocks = (unsigned)((max_records + kRouteChunk - 1) / kRouteChunk + r.nb);
+    const int vec = ((uintptr_t)g_table & 15u) == 0;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table, vec, train_blocks);
+    };
     if (gh.n_feat == 1)
-        hipLaunchKernelGGL(route_accumulate_kernel<1>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
+        go(route_accumulate_kernel<1>);
     else if (gh.n_feat == 2)
-        hipLaunchKernelGGL(route_accumulate_kernel<2>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
+        go(route_accumulate_kernel<2>);
     else
-        hipLaunchKernelGGL(route_accumulate_kernel<4>, dim3(blocks), dim3(512), smem, st, r, gh.n_levels, T, g_table);
+        go(route_accumulate_kernel<4>);
     return hipGetLastError();
 }
 

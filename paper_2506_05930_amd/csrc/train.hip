@@ -200,6 +200,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     E* stH = reinterpret_cast<E*>(smem_raw);
     E* stD = stH + TS::RH * SD;
     __shared__ float red[kTrainWaves];
+    __shared__ float red_max[kTrainWaves];
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
 #pragma unroll
     for (int j = 0; j < TS::ACC; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
     float loss_acc = 0.0f;
+    float rec_max = 0.0f;          // largest |value| this thread wrote into a record
 
     const int64_t iters = (a.batch + kTrainPts - 1) / kTrainPts;
     for (int64_t it = blockIdx.x; it < iters; it += gridDim.x) {
@@ -248,10 +250,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
 #pragma unroll
                 for (int ob = 0; ob < C::WB; ++ob)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float v = h[ob][i];
-                        h[ob][i] = v > 0.0f ? v : (a.act ? a.slope * v : 0.0f);
-                    }
+                    for (int i = 0; i < 4; ++i) h[ob][i] = fmaxf(h[ob][i], a.slope * h[ob][i]);   // 0 <= slope <= 1
                 round_to_dtype<DT, C::WB>(h);
                 stage<DT, C::WB, SD>(stH + TS::hrow(k) * SD, wave, lane, h);
                 if constexpr (k < NL - 1) {
@@ -282,12 +281,13 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
                 float g = 0.0f;
                 if (valid && li < a.n_out) {
                     const float zv = z[ob][i];
-                    const float v = sigmoidf_(zv);
+                    const float e = exp_neg_abs(zv);
+                    const float v = sigmoid_from(zv, e);
                     if (a.labels) {
                         const float y = (float)a.labels[b * a.n_out + li];
                         if (a.loss == 0) {
                             g = v - y;
-                            loss_acc += fmaxf(zv, 0.0f) + log1pf(expf(-fabsf(zv))) - y * zv;
+                            loss_acc += fmaxf(zv, 0.0f) + log1pf(e) - y * zv;
                         } else {
                             g = 2.0f * (v - y) * v * (1.0f - v);
                             loss_acc += (v - y) * (v - y);
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const float h = (float)hk[(16 * ob + 4 * grp + i) * SD];
-                        dh[ob][i] = nd[ob][i] * (h > 0.0f ? 1.0f : (a.act ? a.slope : 0.0f));
+                        dh[ob][i] = h > 0.0f ? nd[ob][i] : a.slope * nd[ob][i];
                     }
             } else {
                 back_layer<DT, C::WB, C::NINB>(packed + a.off_b[0], lane, dh, denc);
@@ -393,6 +393,8 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
                             const uint32_t slot = atomicAdd(&cursor[bkt], 1u);
                             if (slot < end) {
                                 float* dst = a.route.vals + (size_t)slot * (2 * C::F);
+#pragma unroll
+                                for (int j = 0; j < 2 * C::F; ++j) rec_max = fmaxf(rec_max, fabsf(v[j]));
                                 if constexpr (C::F == 2) {
                                     *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
                                 } else {
@@ -444,13 +446,23 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
     // Tiles no wave owns do not exist, but entries of partially covered tiles
     // outside (out, in) are skipped above; every (ro, ci) inside is written
     // exactly once because each tile has one owner.
-    for (int off = 32; off > 0; off >>= 1) loss_acc += __shfl_xor(loss_acc, off);
-    if (lane == 0) red[wave] = loss_acc;
+    for (int off = 32; off > 0; off >>= 1) {
+        loss_acc += __shfl_xor(loss_acc, off);
+        rec_max = fmaxf(rec_max, __shfl_xor(rec_max, off));
+    }
+    if (lane == 0) {
+        red[wave] = loss_acc;
+        red_max[wave] = rec_max;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        float sacc = 0.0f;
-        for (int w = 0; w < kTrainWaves; ++w) sacc += red[w];
+        float sacc = 0.0f, m = 0.0f;
+        for (int w = 0; w < kTrainWaves; ++w) {
+            sacc += red[w];
+            m = fmaxf(m, red_max[w]);
+        }
         a.ws_loss[blockIdx.x] = sacc;
+        if (a.route.enabled) a.route.rec_max[blockIdx.x] = m;
     }
 }
 
@@ -519,10 +531,10 @@ bool train_supported(const GridHost& g, const NetShape& s) {
 // Workspace layout (each part 256-byte aligned):
 //   [G][n_w] partial weight gradients | [G] partial losses |
 //   routed scatter: [nb][G] offsets | [nb] totals | [nb+1] bases | [nb+1] chunk bases |
-//                   [R / chunk + nb] chunk buckets | [R][2F] values | [R] keys
+//                   [R / chunk + nb] chunk buckets | [R][2F] values | [R] keys | [G] record maxima
 // with R = batch * n_levels * 4 records (one per corner x-pair).
 struct WsLayout {
-    int64_t w, loss, offsets, totals, base, chunk_base, chunk_bucket, vals, keys, total;
+    int64_t w, loss, offsets, totals, base, chunk_base, chunk_bucket, vals, keys, rec_max, total;
 };
 
 static int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
@@ -550,6 +562,8 @@ static WsLayout ws_layout(const GridHost& g, int64_t n_w, int64_t batch, int G, 
         o = align256(o + R * 2 * g.n_feat * 4);
         L.keys = o;
         o = align256(o + R * 4);
+        L.rec_max = o;
+        o = align256(o + (int64_t)G * 4);
     }
     L.total = o;
     return L;
@@ -624,6 +638,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         r.chunk_bucket = reinterpret_cast<uint32_t*>(ws + wl.chunk_bucket);
         r.vals = reinterpret_cast<float*>(ws + wl.vals);
         r.keys = reinterpret_cast<uint32_t*>(ws + wl.keys);
+        r.rec_max = reinterpret_cast<float*>(ws + wl.rec_max);
         err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
         if (err == hipSuccess) err = launch_route_prefix(r, G, st);
         if (err != hipSuccess) return err;
@@ -637,7 +652,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     });
     if (err != hipSuccess) return err;
     if (a.route.enabled) {
-        err = launch_route_accumulate(gh, a.route, g_table, batch * gh.n_levels * 4, st);
+        err = launch_route_accumulate(gh, a.route, g_table, batch * gh.n_levels * 4, G, st);
         if (err != hipSuccess) return err;
     }
     const int64_t nthreads = a.n_w + 1;

@@ -79,6 +79,9 @@ def test_param_counts(lib):
     assert lib.nvc_mlp_param_count(ctypes.byref(m(n_in=16, width=32, n_hidden=2, n_out=8, dtype=0))) == 1792
     assert lib.nvc_mlp_param_count(ctypes.byref(m(dtype=7))) == _lib.NVC_ERR_DTYPE
     assert lib.nvc_mlp_param_count(ctypes.byref(m(n_out=129))) == _lib.NVC_ERR_UNSUPPORTED
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(act=1, slope=1.5))) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(act=1, slope=float("nan")))) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_mlp_param_count(ctypes.byref(m(act=1, slope=0.01))) > 0
     assert lib.nvc_mlp_packed_bytes(ctypes.byref(m())) >= 2 * 2 * 12288
 
 
