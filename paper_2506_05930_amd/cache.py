@@ -122,9 +122,9 @@ class NVCache:
             api.nvc_adam(p, g, m, v, self.step, self.lr, self.beta1, self.beta2, self.eps, True, stream, ctr=ctr)
         self.pack(stream)
 
-    def train_step(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
-                   stream=None, ctr=None) -> dict:
-        """Pick `batch` pixels, label them with shadow rays, one gradient pass and one Adam step."""
+    def train_gradients(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int,
+                        bufs: dict | None = None, stream=None, ctr=None) -> dict:
+        """Pick `batch` pixels, label them with shadow rays, one gradient pass (no parameter update)."""
         if bufs is None:
             bufs = {"pix": torch.empty(batch, dtype=torch.int32, device=self.device),
                     "labels": torch.empty((batch, self.mlp.n_out), dtype=torch.uint8, device=self.device)}
@@ -132,20 +132,43 @@ class NVCache:
                               stream, ctr=ctr)
         api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
         self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
+        return bufs
+
+    def train_step(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
+                   stream=None, ctr=None) -> dict:
+        """Pick `batch` pixels, label them with shadow rays, one gradient pass and one Adam step."""
+        bufs = self.train_gradients(pos_unit, pos_scene, lights, spheres, frame, batch, bufs, stream, ctr)
         self.adam(stream, ctr=ctr)
         return bufs
 
     def frame(self, pos_unit, pos_scene, nrm, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
-              stream=None, ctr=None) -> dict:
-        """Inference + WRS + neural DI on every pixel, then one training step."""
+              stream=None, ctr=None, side=None) -> dict:
+        """Inference + WRS + neural DI on every pixel, and one training step.
+
+        Without `side` everything runs in order on `stream`.  With a second
+        stream `side`, the training pixels, labels and gradients run on it
+        beside inference and WRS (they only read the parameters), and Adam
+        runs on `stream` once both are done; the results are the same.
+        """
         if bufs is None:
             n = pos_unit.shape[0]
             bufs = {"vis": torch.empty((n, self.mlp.n_out), dtype=self.vis_dtype, device=self.device)}
-        self.infer(pos_unit, bufs["vis"], stream=stream)
-        bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=stream,
+        if side is None:
+            self.infer(pos_unit, bufs["vis"], stream=stream)
+            bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"),
+                                         stream=stream, ctr=ctr)
+            bufs["train"] = self.train_step(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
+                                            stream=stream, ctr=ctr)
+            return bufs
+        main = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.current_stream()
+        side.wait_stream(main)
+        bufs["train"] = self.train_gradients(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
+                                             stream=side, ctr=ctr)
+        self.infer(pos_unit, bufs["vis"], stream=main)
+        bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=main,
                                      ctr=ctr)
-        bufs["train"] = self.train_step(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
-                                        stream=stream, ctr=ctr)
+        main.wait_stream(side)
+        self.adam(main, ctr=ctr)
         return bufs
 
     # ------------------------------------------------------------ checkpoint
@@ -168,8 +191,9 @@ class FrameGraph:
     """One frame of the cache recorded once into a HIP graph and replayed.
 
     The frame is `NVCache.frame` (inference, WRS + neural DI, training pixels,
-    shadow labels, gradients, Adam, repack) followed by a device-counter
-    increment; the frame number and the Adam step are read from the counters
+    shadow labels, gradients, Adam, repack; the training half on a second
+    stream beside inference unless `concurrent` is False) followed by a
+    device-counter increment; the frame number and the Adam step are read from the counters
     `ctr` (int32 [2]) when the kernels run, so every replay is the next
     frame.  `pre(stream)`, if given, is recorded first (e.g. scene animation
     driven by `ctr`).  Every buffer is allocated before capture; the library
@@ -177,8 +201,9 @@ class FrameGraph:
     """
 
     def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, pre=None,
-                 frame0: int = 0):
+                 frame0: int = 0, concurrent: bool = True):
         self.cache = cache
+        self.side = torch.cuda.Stream(device=cache.device) if concurrent else None
         self.args = (pos_unit, pos_scene, nrm, lights, spheres)
         self.batch = int(batch)
         self.pre = pre
@@ -199,7 +224,7 @@ class FrameGraph:
     def _body(self, stream):
         if self.pre is not None:
             self.pre(stream)
-        self.cache.frame(*self.args, 0, self.batch, self.bufs, stream=stream, ctr=self.ctr)
+        self.cache.frame(*self.args, 0, self.batch, self.bufs, stream=stream, ctr=self.ctr, side=self.side)
         api.nvc_counters_advance(self.ctr, stream)
 
     def run_eager(self):
