@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=655360, help="pixels of the oracle's timed sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=256,
                     help="size of a plain device copy run after timing (counter calibration); 0 = none")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the serial per-stage pass (every launch of the run is then a timed-style frame)")
     ap.add_argument("--loop", type=int, default=0,
                     help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
                          "moving) and print its per-frame report")
@@ -261,18 +263,25 @@ def main():
 
     side = torch.cuda.Stream()
 
-    def step(frame, ev=None):
+    def step(frame, ev=None, kev=None):
         """One frame.  Timed frames run the training half (pixels, labels, gradients) on a second
-        stream beside inference + WRS, joining before Adam; with `ev` every stage runs in order on
-        one stream between events (the per-stage breakdown)."""
+        stream beside inference + WRS, joining before Adam (`kev`: events around the inference and
+        WRS launches on their stream); with `ev` every stage runs in order on one stream between
+        events (the per-stage breakdown)."""
         if ev is None:
             side.wait_stream(stream)
             api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws, side)
             api.nvc_shadow_labels(pos, pix, lights, spheres, labels, side)
             cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=side)
+            if kev is not None:
+                kev[0].record(stream)
             api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis, stream)
+            if kev is not None:
+                kev[1].record(stream)
             api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
                                out["wsum"], out["di"], stream)
+            if kev is not None:
+                kev[2].record(stream)
             stream.wait_stream(side)
             cache.adam(stream)
             return
@@ -299,20 +308,28 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    kevs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     t_start.record(stream)
     for f in range(args.steps):
-        step(args.warmup + f)
+        step(args.warmup + f, kev=kevs[f])
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_per_step = t_start.elapsed_time(t_end) / args.steps
+    # Launch durations of the inference and WRS kernels inside the timed frames (they share the
+    # GPU with the training half).
+    timed_ms = {"infer": float(np.mean([k[0].elapsed_time(k[1]) for k in kevs])),
+                "wrs": float(np.mean([k[1].elapsed_time(k[2]) for k in kevs]))}
 
-    # Per-stage durations from HIP events on the launch stream, over a second pass of `steps` frames.
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
-    for f in range(args.steps):
-        step(args.warmup + args.steps + f, evs[f])
-    torch.cuda.synchronize()
-    stage_ms = {s: float(np.mean([evs[f][i].elapsed_time(evs[f][i + 1]) for f in range(args.steps)]))
-                for i, s in enumerate(STAGES)}
+    # Per-stage durations from HIP events on the launch stream, over a second pass of `steps` frames
+    # that runs every stage in order.
+    stage_ms = None
+    if not args.no_stages:
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(args.steps)]
+        for f in range(args.steps):
+            step(args.warmup + args.steps + f, evs[f])
+        torch.cuda.synchronize()
+        stage_ms = {s: float(np.mean([evs[f][i].elapsed_time(evs[f][i + 1]) for f in range(args.steps)]))
+                    for i, s in enumerate(STAGES)}
     loss = float(cache.loss_buf.item())
 
     if args.calibrate_copy_mib:
@@ -324,26 +341,23 @@ def main():
 
     alg = algorithmic(wl, n_pix, B)
     rates = {}
-    for s, d in alg.items():
-        t = stage_ms[s] / 1e3
-        rates[s] = {k: v / t for k, v in d.items()}
-    # Roofline of the dominant kernel.  infer, wrs and labels are one launch
-    # each, so their event times are those kernels' durations; the train and
-    # adam stages are several launches whose largest is shorter than infer's.
-    dominant = max(("infer", "wrs", "labels"), key=lambda k: stage_ms[k])
-    if dominant == "labels":
-        roof = {"bound": "alu", "achieved": rates["labels"]["ops"] / 1e12, "peak": PEAK_ALU_TOPS,
-                "unit": "Tops/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": rates[dominant]["bytes"] / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    if stage_ms is not None:
+        for s, d in alg.items():
+            t = stage_ms[s] / 1e3
+            rates[s] = {k: v / t for k, v in d.items()}
+    # Roofline of the dominant kernel, infer_kernel (the longest single launch of the frame), from its
+    # average launch duration inside the timed frames.
+    t_inf = timed_ms["infer"] / 1e3
+    roof = {"bound": "hbm", "achieved": alg["infer"]["bytes"] / t_inf / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"infer": "infer_kernel", "wrs": "wrs_kernel", "labels": "labels_kernel"}[dominant]
-    roof["avg_launch_ms"] = stage_ms[dominant]
-    hbm = measured_traffic(dominant, wl)
-    roof["traffic"] = None if hbm is None else hbm / (stage_ms[dominant] / 1e3) / 1e9
+    roof["kernel"] = "infer_kernel"
+    roof["avg_launch_ms"] = timed_ms["infer"]
+    hbm = measured_traffic("infer", wl)
+    roof["traffic"] = None if hbm is None else hbm / t_inf / 1e9
     roof["traffic_bytes_per_launch"] = hbm
 
-    q_infer_wrs = n_pix / ((stage_ms["infer"] + stage_ms["wrs"]) / 1e3)
+    st = stage_ms if stage_ms is not None else timed_ms
+    q_infer_wrs = n_pix / ((st["infer"] + st["wrs"]) / 1e3)
     result = {
         "metric": "visibility queries/s (point x all lights) + ms/frame infer+train+WRS, 1080p x 32",
         "value": n_pix / (ms_per_step / 1e3),
@@ -362,8 +376,9 @@ def main():
                    "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}"},
         "ms_per_frame": ms_per_step,
         "streams": "training half on a second stream beside inference + WRS; stage_ms from a serial pass",
-        "ms_per_frame_serial": round(sum(stage_ms.values()), 4),
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "timed_launch_ms": {k: round(v, 4) for k, v in timed_ms.items()},
+        "ms_per_frame_serial": None if stage_ms is None else round(sum(stage_ms.values()), 4),
+        "stage_ms": None if stage_ms is None else {k: round(v, 4) for k, v in stage_ms.items()},
         "queries_per_s_infer_wrs": q_infer_wrs,
         "point_lights_per_s_infer_wrs": q_infer_wrs * wl.n_lights,
         "stage_rates": {s: {k: round(v / 1e9, 2) for k, v in r.items()} for s, r in rates.items()},

@@ -238,6 +238,133 @@ __device__ inline void encode_lane(const float* __restrict__ table, const GridDe
     }
 }
 
+// ------------------------------------------------------------ per-lane levels
+// A level as one lane sees it, computed once per kernel (a lane always feeds
+// the same levels to the MLP).  The dense and hashed indices share one form:
+// with hx = cx + dx, hy = (cy + dy) * my, hz = (cz + dz) * mz,
+//   dense:  hx + hy + hz            (my = N + 1, mz = (N + 1)^2)
+//   hashed: (hx ^ hy ^ hz) & (T-1)  (my = 2654435761, mz = 805459861)
+// so a wave whose lanes mix dense and hashed levels does not branch.
+struct LevelLane {
+    float Nf;           // N_l
+    int nmax;           // N_l - 1
+    uint32_t my, mz;
+    uint32_t mask;      // T - 1 (hashed)
+    uint32_t base;      // first entry of the level: l * T
+    bool dense;
+    bool valid;         // l < n_levels (else the features are 0)
+};
+
+__device__ inline LevelLane level_lane(const GridDev& g, int l) {
+    LevelLane v;
+    v.valid = l < g.n_levels;
+    const int lc = v.valid ? l : 0;
+    const int N = g.res[lc];
+    v.Nf = (float)N;
+    v.nmax = N - 1;
+    v.dense = (g.dense_mask >> lc) & 1u;
+    const uint32_t n1 = (uint32_t)N + 1u;
+    v.my = v.dense ? n1 : 2654435761u;
+    v.mz = v.dense ? n1 * n1 : 805459861u;
+    v.mask = g.T - 1u;
+    v.base = (uint32_t)lc * g.T;
+    return v;
+}
+
+// Entry indices (level-relative) and fractions of the 8 corners at a level.
+__device__ inline void lane_corners(const LevelLane& v, float x, float y, float z, uint32_t (&idx)[8],
+                                    float (&f)[3]) {
+    const float sx = x * v.Nf, sy = y * v.Nf, sz = z * v.Nf;
+    const int cx = min((int)floorf(sx), v.nmax);
+    const int cy = min((int)floorf(sy), v.nmax);
+    const int cz = min((int)floorf(sz), v.nmax);
+    f[0] = sx - (float)cx;
+    f[1] = sy - (float)cy;
+    f[2] = sz - (float)cz;
+    const uint32_t hx[2] = {(uint32_t)cx, (uint32_t)cx + 1u};
+    const uint32_t y0 = (uint32_t)cy * v.my, z0 = (uint32_t)cz * v.mz;
+    const uint32_t hy[2] = {y0, y0 + v.my}, hz[2] = {z0, z0 + v.mz};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t a = hx[k & 1], b = hy[(k >> 1) & 1], c = hz[k >> 2];
+        idx[k] = v.dense ? a + b + c : (a ^ b ^ c) & v.mask;
+    }
+}
+
+// Trilinear weight of corner k, in the order of level_corners.
+__device__ inline float corner_weight(const float (&f)[3], int k) {
+    const float wx = (k & 1) ? f[0] : 1.0f - f[0];
+    const float wy = (k & 2) ? f[1] : 1.0f - f[1];
+    const float wz = (k & 4) ? f[2] : 1.0f - f[2];
+    return (wx * wy) * wz;
+}
+
+// The lane's encoding features (as encode_lane) from its precomputed levels:
+// all corner indices first, then every gather of every level, then the sums,
+// so the loads of all levels are in flight together.
+template <int F, int NINB>
+__device__ inline void encode_lane_lv(const float* __restrict__ table, const LevelLane (&lv)[NINB][4 / F], float x,
+                                      float y, float z, float (&act)[NINB][4]) {
+    constexpr int NQ = 4 / F;
+    uint32_t idx[NINB][NQ][8];
+    float fr[NINB][NQ][3];
+#pragma unroll
+    for (int b = 0; b < NINB; ++b)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            lane_corners(lv[b][q], x, y, z, idx[b][q], fr[b][q]);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) idx[b][q][k] = lv[b][q].valid ? lv[b][q].base + idx[b][q][k] : 0u;
+        }
+    float val[NINB][NQ][8][F];
+#pragma unroll
+    for (int b = 0; b < NINB; ++b)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float* p = table + (size_t)idx[b][q][k] * F;
+                if constexpr (F == 2) {
+                    const float2 t = *reinterpret_cast<const float2*>(p);
+                    val[b][q][k][0] = t.x;
+                    val[b][q][k][1] = t.y;
+                } else if constexpr (F == 4) {
+                    const float4 t = *reinterpret_cast<const float4*>(p);
+                    val[b][q][k][0] = t.x;
+                    val[b][q][k][1] = t.y;
+                    val[b][q][k][2] = t.z;
+                    val[b][q][k][3] = t.w;
+                } else {
+                    val[b][q][k][0] = p[0];
+                }
+            }
+#pragma unroll
+    for (int b = 0; b < NINB; ++b)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float o[F];
+#pragma unroll
+            for (int j = 0; j < F; ++j) o[j] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const float w = corner_weight(fr[b][q], k);
+#pragma unroll
+                for (int j = 0; j < F; ++j) o[j] = fmaf(w, val[b][q][k][j], o[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < F; ++j) act[b][q * F + j] = lv[b][q].valid ? o[j] : 0.0f;
+        }
+}
+
+// The lane's levels: feature 16b + 4*grp + q*F .. belongs to level (16b + 4*grp + q*F) / F.
+template <int F, int NINB>
+__device__ inline void lane_levels(const GridDev& g, int grp, LevelLane (&lv)[NINB][4 / F]) {
+#pragma unroll
+    for (int b = 0; b < NINB; ++b)
+#pragma unroll
+        for (int q = 0; q < 4 / F; ++q) lv[b][q] = level_lane(g, (16 * b + 4 * grp + q * F) / F);
+}
+
 // Correctly rounded FP32 square root of a positive normal x.  The hardware
 // square root is accurate to 1 ulp but not correctly rounded; with s its
 // result and s-, s+ the neighbouring floats, the exact root lies below the

@@ -206,7 +206,17 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
     const int64_t t0 = (int64_t)lb * per_block;
     const int64_t t1 = min(ntiles, t0 + per_block);
 
+    LevelLane lv[C::NINB][4 / C::F];
+    lane_levels<C::F, C::NINB>(a.g, grp, lv);
     for (int64_t t = t0 + wave; t < t1; t += 4) {
+        // Weight fragments are read from LDS (or L1) in every iteration: the
+        // opaque zero offset stops the compiler from hoisting all of them into
+        // registers, which would cost occupancy.
+        int opq = 0;
+        asm volatile("" : "+s"(opq));
+        const E* w_it[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) w_it[k] = wk[k] + opq;
         float h0[NSUB][C::NINB][4];
 #pragma unroll
         for (int s = 0; s < NSUB; ++s) {
@@ -215,26 +225,26 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
             const float x = clamp_unit(a.pos[pc * 3 + 0]);
             const float y = clamp_unit(a.pos[pc * 3 + 1]);
             const float z = clamp_unit(a.pos[pc * 3 + 2]);
-            encode_lane<C::F, C::NINB>(a.table, a.g, grp, x, y, z, h0[s]);
+            encode_lane_lv<C::F, C::NINB>(a.table, lv, x, y, z, h0[s]);
         }
         float ha[NSUB][C::WB][4], hb[NSUB][C::WB][4];
-        mlp_layer<DT, NSUB, C::NINB, C::WB>(wk[0], lane, h0, ha);
+        mlp_layer<DT, NSUB, C::NINB, C::WB>(w_it[0], lane, h0, ha);
         activate<NSUB, C::WB>(ha, a.slope);
 #pragma unroll
         for (int k = 1; k < C::NHID; ++k) {
             if (k % 2 == 1) {
-                mlp_layer<DT, NSUB, C::WB, C::WB>(wk[k], lane, ha, hb);
+                mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, ha, hb);
                 activate<NSUB, C::WB>(hb, a.slope);
             } else {
-                mlp_layer<DT, NSUB, C::WB, C::WB>(wk[k], lane, hb, ha);
+                mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, hb, ha);
                 activate<NSUB, C::WB>(ha, a.slope);
             }
         }
         float z[NSUB][C::NOUTB][4];
         if (C::NHID % 2 == 1)
-            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(wk[NL - 1], lane, ha, z);
+            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, ha, z);
         else
-            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(wk[NL - 1], lane, hb, z);
+            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, hb, z);
 
 #pragma unroll
         for (int s = 0; s < NSUB; ++s) {
