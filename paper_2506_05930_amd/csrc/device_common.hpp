@@ -375,11 +375,9 @@ __device__ inline float sqrt_rn(float x) {
     float s = __builtin_amdgcn_sqrtf(x);
     const float s_dn = __int_as_float(__float_as_int(s) - 1);
     const float s_up = __int_as_float(__float_as_int(s) + 1);
-    if (fmaf(-s_dn, s, x) <= 0.0f)
-        s = s_dn;
-    else if (fmaf(-s_up, s, x) > 0.0f)
-        s = s_up;
-    return s;
+    const bool down = fmaf(-s_dn, s, x) <= 0.0f;
+    const bool up = fmaf(-s_up, s, x) > 0.0f;
+    return down ? s_dn : (up ? s_up : s);            // selects, no branches
 }
 
 // exp(-|z|) with the hardware base-2 exponential (within 1 ulp of exp2 of

@@ -14,22 +14,68 @@ namespace nvc {
 
 // ------------------------------------------------------------------ WRS
 // One thread per pixel; the lights sit in LDS and every lane reads the same
-// light at the same time (broadcast).  The weights are kept in registers
-// (MAXM >= m) and scanned sequentially in light order.
-template <int MAXM, typename VT>
-__global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, int64_t n, int m,
-                                                 const float* __restrict__ pos, const float* __restrict__ nrm,
-                                                 const float* __restrict__ lights, float vis_floor, uint32_t k0,
-                                                 uint32_t k1, uint32_t frame, const uint32_t* __restrict__ frame_dev,
-                                                 int32_t* __restrict__ idx_out,
-                                                 float* __restrict__ pmf_out, float* __restrict__ wsum_out,
-                                                 float* __restrict__ di_out) {
-    __shared__ float4 L[MAXM];
+// light at the same time (broadcast).  Lights are taken in groups of eight
+// (one vector load of the visibilities when the rows allow it).  Pass 1 runs
+// the sequential FP32 sum W = C_{m-1} and keeps the running sum at the end of
+// every group in LDS; pass 2 finds the first group whose end exceeds u * W
+// (the sum never decreases, so the pick lies in it) and recomputes that
+// group's eight weights with the same operations from the sum before it,
+// which reproduces C_i exactly.
+constexpr int kWrsThreads = 256;
+
+// Unshadowed weight f and light weight w = f * max(v, floor) of light l at p (order as in nvc.h).
+__device__ inline void wrs_weight(const float4& l, float px, float py, float pz, float nx, float ny, float nz,
+                                  bool has_n, float v, float vis_floor, float& f, float& w) {
+    const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
+    const float d2 = fmaxf((dx * dx + dy * dy) + dz * dz, 1e-6f);
+    if (has_n) {
+        const float nd = (nx * dx + ny * dy) + nz * dz;
+        f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
+    } else {
+        f = __fdiv_rn(l.w, d2);
+    }
+    w = f * fmaxf(v, vis_floor);
+}
+
+// The eight visibilities of group g of a row (missing lights read as 0).
+template <typename VT>
+__device__ inline void wrs_load8(const VT* __restrict__ row, int g, int m, bool vec, float (&v)[8]) {
+    const int i0 = 8 * g;
+    if (vec && i0 + 8 <= m) {
+        if constexpr (sizeof(VT) == 4) {
+            const float4 a = reinterpret_cast<const float4*>(row + i0)[0];
+            const float4 b = reinterpret_cast<const float4*>(row + i0)[1];
+            v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+            v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        } else {
+            typedef VT v8 __attribute__((ext_vector_type(8)));
+            const v8 a = *reinterpret_cast<const v8*>(row + i0);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (float)a[j];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = i0 + j < m ? (float)row[i0 + j] : 0.0f;
+    }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__ vis, int64_t n, int m,
+                                                         const float* __restrict__ pos,
+                                                         const float* __restrict__ nrm,
+                                                         const float* __restrict__ lights, float vis_floor,
+                                                         uint32_t k0, uint32_t k1, uint32_t frame,
+                                                         const uint32_t* __restrict__ frame_dev, int vec,
+                                                         int32_t* __restrict__ idx_out, float* __restrict__ pmf_out,
+                                                         float* __restrict__ wsum_out, float* __restrict__ di_out) {
+    __shared__ float4 L[128];
+    __shared__ float cend[16][kWrsThreads];       // running sum at the end of each group of 8 lights
     for (int i = threadIdx.x; i < m; i += blockDim.x)
         L[i] = make_float4(lights[4 * i + 0], lights[4 * i + 1], lights[4 * i + 2], lights[4 * i + 3]);
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    const int tid = threadIdx.x;
     const float px = pos[p * 3 + 0], py = pos[p * 3 + 1], pz = pos[p * 3 + 2];
     float nx = 0.f, ny = 0.f, nz = 0.f;
     const bool has_n = nrm != nullptr;
@@ -38,51 +84,66 @@ __global__ __launch_bounds__(256) void wrs_kernel(const VT* __restrict__ vis, in
         ny = nrm[p * 3 + 1];
         nz = nrm[p * 3 + 2];
     }
-    const VT* vrow = vis + p * (int64_t)m;
-    float w[MAXM];
-    float W = 0.0f, di = 0.0f;
+    const VT* row = vis + p * (int64_t)m;
+    const int ng = (m + 7) / 8;
+    float W = 0.0f, di = 0.0f, wlast = 0.0f;
+    int last_pos = -1;
+    for (int g = 0; g < ng; ++g) {
+        float v[8];
+        wrs_load8(row, g, m, vec != 0, v);
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-        w[i] = 0.0f;
-        if (i < m) {
-            const float4 l = L[i];
-            const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
-            const float d2 = fmaxf((dx * dx + dy * dy) + dz * dz, 1e-6f);
-            float f;
-            if (has_n) {
-                const float nd = (nx * dx + ny * dy) + nz * dz;
-                f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
-            } else {
-                f = __fdiv_rn(l.w, d2);
+        for (int j = 0; j < 8; ++j) {
+            const int i = 8 * g + j;
+            if (i < m) {
+                float f, w;
+                wrs_weight(L[i], px, py, pz, nx, ny, nz, has_n, v[j], vis_floor, f, w);
+                W = W + w;
+                di = fmaf(v[j], f, di);
+                if (w > 0.0f) {
+                    last_pos = i;
+                    wlast = w;
+                }
             }
-            const float v = (float)vrow[i];
-            w[i] = f * fmaxf(v, vis_floor);
-            W = W + w[i];
-            di = fmaf(v, f, di);
         }
+        cend[g][tid] = W;
     }
     const uint32_t fr = frame_dev ? *frame_dev : frame;
     const uint32_t r0 = philox_first_word((uint32_t)p, (uint32_t)((uint64_t)p >> 32), fr, 0u, k0, k1);
     const float u = (float)(r0 >> 8) * 0x1.0p-24f;
     const float t = u * W;
-    int pick = -1, last_pos = -1;
-    float C = 0.0f, wsel = 0.0f;
+    int pick = -1;
+    float wsel = 0.0f;
+    int gs = -1;
+    float c0 = 0.0f;
+    for (int g = 0; g < ng; ++g) {
+        const float ce = cend[g][tid];
+        if (ce > t) {
+            gs = g;
+            break;
+        }
+        c0 = ce;
+    }
+    if (gs >= 0) {
+        float v[8];
+        wrs_load8(row, gs, m, vec != 0, v);
+        float C = c0;
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) {
-        if (i < m) {
-            C = C + w[i];
-            if (w[i] > 0.0f) last_pos = i;
-            if (pick < 0 && C > t) {
-                pick = i;
-                wsel = w[i];
+        for (int j = 0; j < 8; ++j) {
+            const int i = 8 * gs + j;
+            if (i < m) {
+                float f, w;
+                wrs_weight(L[i], px, py, pz, nx, ny, nz, has_n, v[j], vis_floor, f, w);
+                C = C + w;
+                if (pick < 0 && C > t) {
+                    pick = i;
+                    wsel = w;
+                }
             }
         }
     }
     if (pick < 0 && last_pos >= 0) {          // only through rounding
         pick = last_pos;
-#pragma unroll
-        for (int i = 0; i < MAXM; ++i)
-            if (i == last_pos) wsel = w[i];
+        wsel = wlast;
     }
     if (!(W > 0.0f)) pick = -1;
     idx_out[p] = pick;
@@ -95,19 +156,10 @@ template <typename VT>
 static void run_wrs(const VT* vis, int64_t n, int m, const float* pos, const float* nrm, const float* lights,
                     float vis_floor, uint32_t k0, uint32_t k1, uint32_t frame, const uint32_t* frame_dev,
                     int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st) {
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    auto go = [&](auto kernel) {
-        kernel<<<blocks, 256, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf,
-                                       wsum, di);
-    };
-    if (m <= 8)
-        go(wrs_kernel<8, VT>);
-    else if (m <= 32)
-        go(wrs_kernel<32, VT>);
-    else if (m <= 64)
-        go(wrs_kernel<64, VT>);
-    else
-        go(wrs_kernel<128, VT>);
+    const unsigned blocks = (unsigned)((n + kWrsThreads - 1) / kWrsThreads);
+    const int vec = m % 8 == 0 && ((uintptr_t)vis & 15u) == 0;
+    wrs_kernel<VT><<<blocks, kWrsThreads, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev,
+                                                    vec, idx, pmf, wsum, di);
 }
 
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
