@@ -52,6 +52,9 @@ def parse():
                     help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
                          "moving) and print its per-frame report")
     ap.add_argument("--loop-eval", type=int, default=65536, help="pixels of the loop's fixed evaluation subset")
+    ap.add_argument("--mlp", action="store_true",
+                    help="instead: time the MLP alone (nvc_mlp_forward) on the frame's encoding and report its "
+                         "matrix-core throughput")
     return ap.parse_args()
 
 
@@ -162,6 +165,37 @@ def estimator_stats(f, V, v, floor):
     return out
 
 
+PEAK_MFMA_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "f32": 157.3}
+
+
+def run_mlp(args, wl, cache, pos_unit, dev):
+    """The MLP of the frame alone, on its stored encoding: matrix-core FLOP/s against the dtype's peak."""
+    import numpy as np
+    import torch
+
+    from paper_2506_05930_amd import api
+    n = pos_unit.shape[0]
+    enc = cache.encode(pos_unit, dtype=cache.vis_dtype)
+    vis = torch.empty((n, wl.mlp.n_out), dtype=cache.vis_dtype, device=dev)
+    for _ in range(args.warmup):
+        api.nvc_mlp_forward(cache.mlp, cache.packed, enc, vis)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    for e in evs:
+        e[0].record()
+        api.nvc_mlp_forward(cache.mlp, cache.packed, enc, vis)
+        e[1].record()
+    torch.cuda.synchronize()
+    ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    flops = n * wl.mlp.flops_per_point
+    io = n * (wl.mlp.n_in + wl.mlp.n_out) * vis.element_size()
+    tf = flops / (ms / 1e3) / 1e12
+    return {"workload": wl.name, "kernel": "infer_kernel (encoding read from memory)", "dtype": wl.mlp.dtype,
+            "points": n, "flops_per_point": wl.mlp.flops_per_point, "ms": ms, "tflops": tf,
+            "peak_tflops": PEAK_MFMA_TFLOPS[wl.mlp.dtype], "mfma_frac": tf / PEAK_MFMA_TFLOPS[wl.mlp.dtype],
+            "io_bytes": io, "io_gbs": io / (ms / 1e3) / 1e9, "steps": args.steps}
+
+
 def run_loop(args, wl, cache, scene, tens, dev):
     """The frame loop: light 0 moves on a circle; each frame is one replay of a recorded HIP graph."""
     import numpy as np
@@ -259,6 +293,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.loop:
         print(json.dumps(run_loop(args, wl, cache, scene, (pos_unit, pos, nrm, lights, spheres), dev)))
+        return
+    if args.mlp:
+        print(json.dumps(run_mlp(args, wl, cache, pos_unit, dev)))
         return
 
     side = torch.cuda.Stream()

@@ -125,6 +125,14 @@ int nvc_encode(const nvc_grid* grid, const float* table, const float* pos, int64
 int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
               const float* pos, int64_t n, void* vis, int32_t vis_dtype, void* stream);
 
+/* The MLP of nvc_infer alone (Sec. 3.3), on a given encoding: enc [n][n_in]
+ * in enc_dtype (e.g. the output of nvc_encode), vis [n][n_out] in vis_dtype.
+ * The encoding is rounded to mlp->dtype for the matrix cores, as inside
+ * nvc_infer, so nvc_mlp_forward(nvc_encode(x)) with enc_dtype = mlp->dtype
+ * (or FP32) equals nvc_infer(x).  Same network shapes as nvc_infer. */
+int nvc_mlp_forward(const nvc_mlp* mlp, const void* packed, const void* enc, int32_t enc_dtype, int64_t n,
+                    void* vis, int32_t vis_dtype, void* stream);
+
 /* Per-frame counters in DEVICE memory, for frames recorded once into a HIP
  * graph and replayed: nvc_sample_wrs and nvc_select_pixels given a non-NULL
  * `ctr` take the frame number from ctr->frame, and nvc_adam takes its step

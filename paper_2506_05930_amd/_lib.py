@@ -25,7 +25,7 @@ NVC_LOSS_BCE, NVC_LOSS_L2 = 0, 1
 
 EXPORTS = [
     "nvc_version", "nvc_status_string", "nvc_grid_levels", "nvc_mlp_param_count", "nvc_mlp_packed_bytes",
-    "nvc_pack_mlp", "nvc_encode", "nvc_infer", "nvc_sample_wrs", "nvc_select_pixels_workspace_bytes",
+    "nvc_pack_mlp", "nvc_encode", "nvc_infer", "nvc_mlp_forward", "nvc_sample_wrs", "nvc_select_pixels_workspace_bytes",
     "nvc_select_pixels", "nvc_shadow_labels",
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
 ]
@@ -57,6 +57,7 @@ _SIGS = {
     "nvc_encode": (c_int32, [POINTER(NvcGrid), c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p]),
     "nvc_infer": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
                             c_int32, c_void_p]),
+    "nvc_mlp_forward": (c_int32, [POINTER(NvcMlp), c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int32, c_void_p]),
     "nvc_sample_wrs": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_float,
                                  c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nvc_select_pixels_workspace_bytes": (c_int64, [c_int64]),

@@ -134,6 +134,15 @@ def nvc_counters_advance(ctr: torch.Tensor, stream=None) -> None:
     _lib.check("nvc_counters_advance", _lib.load().nvc_counters_advance(_counters(ctr), _stream(stream)))
 
 
+def nvc_mlp_forward(mlp: NvcMlp, packed: torch.Tensor, enc: torch.Tensor, vis: torch.Tensor, stream=None) -> None:
+    n = enc.shape[0]
+    pk = _ptr(packed, "packed")
+    pe = _ptr(enc, "enc", (torch.float32, torch.float16, torch.bfloat16), (n, mlp.n_in))
+    pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16), (n, mlp.n_out))
+    _lib.check("nvc_mlp_forward", _lib.load().nvc_mlp_forward(ctypes.byref(mlp), pk, pe, _DT_CODE[enc.dtype], n, pv,
+                                                              _DT_CODE[vis.dtype], _stream(stream)))
+
+
 def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, vis_floor: float, seed: int,
                    frame: int, idx: torch.Tensor, pmf: torch.Tensor, wsum: torch.Tensor, di=None,
                    stream=None, ctr=None) -> None:

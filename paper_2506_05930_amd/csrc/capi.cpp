@@ -152,6 +152,20 @@ int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, cons
     return hip_status(launch_infer(g, s, p, table, packed, pos, n, vis, vis_dtype, (hipStream_t)stream));
 }
 
+int nvc_mlp_forward(const nvc_mlp* mlp, const void* packed, const void* enc, int32_t enc_dtype, int64_t n, void* vis,
+                    int32_t vis_dtype, void* stream) {
+    NetShape s{};
+    const int st = check_mlp(mlp, &s);
+    if (st) return st;
+    if (!valid_dtype(enc_dtype) || !valid_dtype(vis_dtype)) return NVC_ERR_DTYPE;
+    if (n < 0) return NVC_ERR_SHAPE;
+    if (!mlp_supported(s)) return NVC_ERR_UNSUPPORTED;
+    if (n == 0) return NVC_OK;
+    if (!packed || !enc || !vis) return NVC_ERR_NULL;
+    const PackPlan p = make_pack_plan(s);
+    return hip_status(launch_mlp_forward(s, p, packed, enc, enc_dtype, n, vis, vis_dtype, (hipStream_t)stream));
+}
+
 int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m, const float* pos, const float* nrm,
                    const float* lights, float vis_floor, uint64_t seed, uint32_t frame, const nvc_counters* ctr,
                    int32_t* idx, float* pmf, float* wsum, float* di, void* stream) {

@@ -233,7 +233,10 @@ __device__ inline void encode_lane(const float* __restrict__ table, const GridDe
                 for (int j = 0; j < F; ++j) v[j] = 0.0f;
             }
 #pragma unroll
-            for (int j = 0; j < F; ++j) act[b][q + j] = v[j];
+            for (int j = 0; j < F; ++j) {
+                asm volatile("" : "+v"(v[j]));      // an FP32 value (see encode_lane_lv)
+                act[b][q + j] = v[j];
+            }
         }
     }
 }
@@ -352,7 +355,13 @@ __device__ inline void encode_lane_lv(const float* __restrict__ table, const Lev
                 for (int j = 0; j < F; ++j) o[j] = fmaf(w, val[b][q][k][j], o[j]);
             }
 #pragma unroll
-            for (int j = 0; j < F; ++j) act[b][q * F + j] = lv[b][q].valid ? o[j] : 0.0f;
+            for (int j = 0; j < F; ++j) {
+                // The feature is an FP32 value: the empty asm keeps the compiler from
+                // folding the last FMA into the conversion to the matrix-core dtype
+                // (v_fma_mix rounds once, straight to FP16).
+                asm volatile("" : "+v"(o[j]));
+                act[b][q * F + j] = lv[b][q].valid ? o[j] : 0.0f;
+            }
         }
 }
 

@@ -154,9 +154,58 @@ struct InferArgs {
     int act;
     float slope;
     int vec_ok;           // rows start 4-element aligned and vis is 16-byte aligned: vector stores
+    const void* enc;      // pre-computed encoding [n][n_in] (nvc_mlp_forward), else nullptr
+    int enc_dtype;
+    int n_in;
+    int enc_vec;          // n_in % 4 == 0 and enc 16-byte aligned
 };
 
-template <class C>
+// Encoding features of point p a lane owns (layout of encode_lane), read from
+// a pre-computed [n][n_in] buffer and rounded to FP32.  vec: n_in is a
+// multiple of 4 and the buffer 16-byte aligned, so a lane's four features of
+// a block are one aligned load.
+template <int NINB>
+__device__ inline void load_lane_encoding(const void* enc, int enc_dtype, int n_in, bool vec, int64_t p, int grp,
+                                          float (&act)[NINB][4]) {
+#pragma unroll
+    for (int b = 0; b < NINB; ++b) {
+        const int f0 = 16 * b + 4 * grp;
+        const int64_t o = p * n_in + f0;
+        if (vec && f0 + 4 <= n_in) {
+            if (enc_dtype == DT_F32) {
+                const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(enc) + o);
+                act[b][0] = v.x; act[b][1] = v.y; act[b][2] = v.z; act[b][3] = v.w;
+            } else if (enc_dtype == DT_F16) {
+                typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+                const h4 v = *reinterpret_cast<const h4*>(reinterpret_cast<const _Float16*>(enc) + o);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) act[b][i] = (float)v[i];
+            } else {
+                typedef __bf16 b4 __attribute__((ext_vector_type(4)));
+                const b4 v = *reinterpret_cast<const b4*>(reinterpret_cast<const __bf16*>(enc) + o);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) act[b][i] = (float)v[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = 0.0f;
+                if (f0 + i < n_in) {
+                    if (enc_dtype == DT_F32)
+                        v = reinterpret_cast<const float*>(enc)[o + i];
+                    else if (enc_dtype == DT_F16)
+                        v = (float)reinterpret_cast<const _Float16*>(enc)[o + i];
+                    else
+                        v = (float)reinterpret_cast<const __bf16*>(enc)[o + i];
+                }
+                act[b][i] = v;
+            }
+        }
+    }
+}
+
+// PRE: the encoding comes from a.enc (nvc_mlp_forward) instead of the table.
+template <class C, bool PRE>
 __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
     constexpr int DT = C::DT;
     using M = Mma<DT>;
@@ -207,7 +256,7 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
     const int64_t t1 = min(ntiles, t0 + per_block);
 
     LevelLane lv[C::NINB][4 / C::F];
-    lane_levels<C::F, C::NINB>(a.g, grp, lv);
+    if constexpr (!PRE) lane_levels<C::F, C::NINB>(a.g, grp, lv);
     for (int64_t t = t0 + wave; t < t1; t += 4) {
         // Weight fragments are read from LDS (or L1) in every iteration: the
         // opaque zero offset stops the compiler from hoisting all of them into
@@ -222,10 +271,14 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
         for (int s = 0; s < NSUB; ++s) {
             const int64_t p = t * PTS + s * 16 + col;
             const int64_t pc = p < a.n ? p : a.n - 1;
-            const float x = clamp_unit(a.pos[pc * 3 + 0]);
-            const float y = clamp_unit(a.pos[pc * 3 + 1]);
-            const float z = clamp_unit(a.pos[pc * 3 + 2]);
-            encode_lane_lv<C::F, C::NINB>(a.table, lv, x, y, z, h0[s]);
+            if constexpr (PRE) {
+                load_lane_encoding<C::NINB>(a.enc, a.enc_dtype, a.n_in, a.enc_vec != 0, pc, grp, h0[s]);
+            } else {
+                const float x = clamp_unit(a.pos[pc * 3 + 0]);
+                const float y = clamp_unit(a.pos[pc * 3 + 1]);
+                const float z = clamp_unit(a.pos[pc * 3 + 2]);
+                encode_lane_lv<C::F, C::NINB>(a.table, lv, x, y, z, h0[s]);
+            }
         }
         float ha[NSUB][C::WB][4], hb[NSUB][C::WB][4];
         mlp_layer<DT, NSUB, C::NINB, C::WB>(w_it[0], lane, h0, ha);
@@ -302,8 +355,12 @@ int cu_count() { return device_cu_count_impl(); }
 template <class C>
 static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float* table, const void* packed,
                             const float* pos, int64_t n, int n_out, void* vis, int vis_dtype, int act, float slope,
-                            hipStream_t st) {
+                            const void* enc, int enc_dtype, int n_in, hipStream_t st) {
     InferArgs a{};
+    a.enc = enc;
+    a.enc_dtype = enc_dtype;
+    a.n_in = n_in;
+    a.enc_vec = n_in % 4 == 0 && ((uintptr_t)enc % 16) == 0;
     a.g = g;
     a.table = table;
     a.packed = packed;
@@ -325,7 +382,10 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     int64_t want = (ntiles + 3) / 4;                        // at least one tile per wave
     int64_t G = std::min<int64_t>(want, (int64_t)cu_count() * per_cu);
     G = std::max<int64_t>(8, (G + 7) / 8 * 8);
-    hipLaunchKernelGGL(infer_kernel<C>, dim3((unsigned)G), dim3(256), smem, st, a);
+    if (enc)
+        hipLaunchKernelGGL((infer_kernel<C, true>), dim3((unsigned)G), dim3(256), smem, st, a);
+    else
+        hipLaunchKernelGGL((infer_kernel<C, false>), dim3((unsigned)G), dim3(256), smem, st, a);
     return hipGetLastError();
 }
 
@@ -348,7 +408,29 @@ hipError_t launch_infer(const GridHost& g, const NetShape& s, const PackPlan& pl
     hipError_t err = hipErrorNotSupported;
     const GridDev gd = to_dev(g);
     dispatch_config(g.n_feat, s, [&]<class C>() {
-        err = run_infer<C>(gd, plan, table, packed, pos, n, s.n_out, vis, vis_dtype, s.act, s.slope, st);
+        err = run_infer<C>(gd, plan, table, packed, pos, n, s.n_out, vis, vis_dtype, s.act, s.slope, nullptr, 0,
+                           s.n_in, st);
+    });
+    return err;
+}
+
+// The MLP alone on a given encoding: the configurations differ in features
+// per level only through the encoding, so any matching one serves.
+static int mlp_feat(const NetShape& s) {
+    for (int F : {2, 4, 1})
+        if (dispatch_config(F, s, [&]<class C>() {})) return F;
+    return 0;
+}
+
+bool mlp_supported(const NetShape& s) { return mlp_feat(s) != 0; }
+
+hipError_t launch_mlp_forward(const NetShape& s, const PackPlan& plan, const void* packed, const void* enc,
+                              int enc_dtype, int64_t n, void* vis, int vis_dtype, hipStream_t st) {
+    hipError_t err = hipErrorNotSupported;
+    const GridDev gd{};
+    dispatch_config(mlp_feat(s), s, [&]<class C>() {
+        err = run_infer<C>(gd, plan, nullptr, packed, nullptr, n, s.n_out, vis, vis_dtype, s.act, s.slope, enc,
+                           enc_dtype, s.n_in, st);
     });
     return err;
 }

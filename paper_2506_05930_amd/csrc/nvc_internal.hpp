@@ -58,6 +58,9 @@ hipError_t launch_encode(const GridHost& g, const float* table, const float* pos
 hipError_t launch_infer(const GridHost& g, const NetShape& s, const PackPlan& plan, const float* table,
                         const void* packed, const float* pos, int64_t n, void* vis, int vis_dtype, hipStream_t st);
 bool infer_supported(const GridHost& g, const NetShape& s);
+bool mlp_supported(const NetShape& s);
+hipError_t launch_mlp_forward(const NetShape& s, const PackPlan& plan, const void* packed, const void* enc,
+                              int enc_dtype, int64_t n, void* vis, int vis_dtype, hipStream_t st);
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
                       const float* lights, float vis_floor, uint64_t seed, uint32_t frame,
                       const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st);

@@ -124,6 +124,31 @@ def test_infer_outputs_in_every_dtype_agree():
         assert torch.equal(cache.infer(pos, dtype=dt), v32.to(dt))
 
 
+@pytest.mark.parametrize("wl_name,dtype", [(w, d) for w in ("tiny", "frame_1080p", "sweep_4k") for d in ("f32", "f16", "bf16")]
+                         + [("paper", "f16"), ("paper", "f32")])
+def test_mlp_forward_on_encoding_equals_fused_inference(wl_name, dtype):
+    """nvc_mlp_forward(nvc_encode(x)) reproduces nvc_infer(x) bit for bit, with the encoding stored
+    in the network's dtype and in FP32 (both round to the same matrix-core inputs)."""
+    from paper_2506_05930_amd import api
+    if wl_name == "paper":                     # ten levels of four features, leaky ReLU (Sec. 3.3)
+        from paper_2506_05930_amd.cache import NVCache
+        from workloads import GridCfg, MlpCfg, init_params
+        grid = GridCfg(n_levels=10, n_feat=4, log2_T=14, base_res=16, growth=1.5)
+        m = MlpCfg(n_in=40, width=32, n_hidden=2, n_out=32, act="leaky", leaky_slope=0.01, dtype=dtype)
+        p = init_params(1, grid, m, table_scale=1.0, weight_gain=2.0, init="he")
+        cache = NVCache(grid, m, p["table"], p["weights"], device=DEV)
+    else:
+        wl = get_workload(wl_name)
+        cache = make_cache(wl, params(wl), dtype=dtype)
+    pos = t(rand_pos(17, 2085))
+    ref = cache.infer(pos, dtype=torch.float32)
+    for enc_dt in {api.torch_dtype(cache.mlp.dtype), torch.float32}:
+        enc = cache.encode(pos, dtype=enc_dt)
+        out = torch.empty_like(ref)
+        api.nvc_mlp_forward(cache.mlp, cache.packed, enc, out)
+        assert torch.equal(out, ref), (wl_name, dtype, enc_dt)
+
+
 # ----------------------------------------------------------------- WRS
 @pytest.mark.parametrize("m,with_n,floor", [(8, False, 1e-3), (32, True, 1e-3), (32, True, 0.0), (128, True, 1e-3),
                                             (20, True, 1e-3)])
