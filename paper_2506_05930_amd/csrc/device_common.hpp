@@ -403,4 +403,11 @@ __device__ inline float sigmoid_from(float z, float e) {
 
 __device__ inline float sigmoidf_(float z) { return sigmoid_from(z, exp_neg_abs(z)); }
 
+// 1 / (1 + exp(-z)) from the hardware exp2 and reciprocal without the stable
+// split: exp2 overflows to +inf for very negative z and the reciprocal gives
+// 0; relative error a few 1e-7 (as sigmoidf_ for |z| < 16).
+__device__ inline float sigmoid_fast(float z) {
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.44269504088896341f));
+}
+
 }  // namespace nvc

@@ -117,14 +117,21 @@ __device__ inline void mlp_layer(const typename Mma<DT>::elem* W, int lane, cons
 
 template <int NSUB, int NB>
 __device__ inline void activate(float (&a)[NSUB][NB][4], float slope) {
+    if (slope == 0.0f) {       // ReLU: a float with the sign bit set is a negative int32, so max(bits, 0) is one op
 #pragma unroll
-    for (int s = 0; s < NSUB; ++s)
+        for (int s = 0; s < NSUB; ++s)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[s][b][i] = fmaxf(a[s][b][i], slope * a[s][b][i]);   // ReLU (slope 0) or leaky, 0 <= slope <= 1
-            }
+                for (int i = 0; i < 4; ++i) a[s][b][i] = __int_as_float(max(__float_as_int(a[s][b][i]), 0));
+    } else {                   // leaky, 0 < slope <= 1
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[s][b][i] = fmaxf(a[s][b][i], slope * a[s][b][i]);
+    }
 }
 
 // Fragments of the forward matrices, compact in LDS: layer 0, hidden layers, output layer.
@@ -204,9 +211,14 @@ __device__ inline void load_lane_encoding(const void* enc, int enc_dtype, int n_
     }
 }
 
+// Waves per block: eight for the 128-wide network (twelve when the encoding
+// is read from memory: fewer registers), whose weights fill most of the LDS
+// (one block per CU); four otherwise.
+template <class C, bool PRE> constexpr int infer_waves() { return C::WB >= 8 ? (PRE ? 12 : 8) : 4; }
+
 // PRE: the encoding comes from a.enc (nvc_mlp_forward) instead of the table.
 template <class C, bool PRE>
-__global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
+__global__ __launch_bounds__((64 * infer_waves<C, PRE>())) void infer_kernel(InferArgs a) {
     constexpr int DT = C::DT;
     using M = Mma<DT>;
     using E = typename M::elem;
@@ -257,7 +269,7 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
 
     LevelLane lv[C::NINB][4 / C::F];
     if constexpr (!PRE) lane_levels<C::F, C::NINB>(a.g, grp, lv);
-    for (int64_t t = t0 + wave; t < t1; t += 4) {
+    for (int64_t t = t0 + wave; t < t1; t += infer_waves<C, PRE>()) {
         // Weight fragments are read from LDS (or L1) in every iteration: the
         // opaque zero offset stops the compiler from hoisting all of them into
         // registers, which would cost occupancy.
@@ -308,7 +320,7 @@ __global__ __launch_bounds__(256) void infer_kernel(InferArgs a) {
                 const int l0 = 16 * ob + 4 * grp;
                 float v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = sigmoidf_(z[s][ob][i]);
+                for (int i = 0; i < 4; ++i) v[i] = sigmoid_fast(z[s][ob][i]);
                 const int64_t base = p * a.n_out + l0;
                 if (a.vec_ok && l0 + 4 <= a.n_out) {
                     if (a.vis_dtype == DT_F32) {
@@ -379,13 +391,14 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     const int64_t pts = 16 * C::NSUB_INFER;
     const int64_t ntiles = (n + pts - 1) / pts;
     const int per_cu = smem > 80 * 1024 ? 1 : (smem > 40 * 1024 ? 2 : 4);
-    int64_t want = (ntiles + 3) / 4;                        // at least one tile per wave
+    const int IW = enc ? infer_waves<C, true>() : infer_waves<C, false>();
+    int64_t want = (ntiles + IW - 1) / IW;                  // at least one tile per wave
     int64_t G = std::min<int64_t>(want, (int64_t)cu_count() * per_cu);
     G = std::max<int64_t>(8, (G + 7) / 8 * 8);
     if (enc)
-        hipLaunchKernelGGL((infer_kernel<C, true>), dim3((unsigned)G), dim3(256), smem, st, a);
+        hipLaunchKernelGGL((infer_kernel<C, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
     else
-        hipLaunchKernelGGL((infer_kernel<C, false>), dim3((unsigned)G), dim3(256), smem, st, a);
+        hipLaunchKernelGGL((infer_kernel<C, false>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
     return hipGetLastError();
 }
 
