@@ -100,7 +100,9 @@ int64_t nvc_mlp_param_count(const nvc_mlp* mlp);
 /* Host only.  Bytes of the packed low-precision copy of the weights that
  * nvc_infer and nvc_train_step read, or a negative status.  The packed copy
  * holds, per layer, the matrix and its transpose cut into matrix-core
- * operand fragments, in mlp->dtype. */
+ * operand fragments, in mlp->dtype; for 16-bit networks whose output count
+ * spans an even number of 16-neuron blocks, also a copy of the output
+ * layer with its rows in the order the inference kernel stores them. */
 int64_t nvc_mlp_packed_bytes(const nvc_mlp* mlp);
 
 /* Cast and reorder FP32 master weights `w` (nvc_mlp_param_count floats) into

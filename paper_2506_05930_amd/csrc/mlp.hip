@@ -35,6 +35,15 @@ PackPlan make_pack_plan(const NetShape& s) {
         off += (int64_t)L.nb_out_f * L.kc_in_f * 64 * epl(s.dtype);
         L.off_b = off;
         off += (int64_t)L.nb_in_b * L.kc_out_b * 64 * epl(s.dtype);
+        L.off_o = L.off_f;
+        L.gb_o = 1;
+    }
+    // 16-bit inference stores pairs of output blocks (out_neuron order).
+    LayerPack& O = p.layer[p.n_layers - 1];
+    if (s.dtype != DT_F32 && O.nb_out_f % 2 == 0) {
+        O.gb_o = 2;
+        O.off_o = off;
+        off += (int64_t)O.nb_out_f * O.kc_in_f * 64 * epl(s.dtype);
     }
     p.total_elems = off;
     return p;
@@ -51,14 +60,15 @@ __global__ void pack_kernel(PackPlan plan, const float* __restrict__ w, typename
     const LayerPack& L = plan.layer[k];
     const float* W = w + L.w_off;
     float v = 0.0f;
-    if (e < L.off_b) {                       // forward: A[row = out neuron][K = in neuron]
-        const int64_t r = e - L.off_f;
+    const bool inf_copy = L.off_o != L.off_f && e >= L.off_o;
+    if (e < L.off_b || inf_copy) {           // forward: A[row = out neuron][K = in neuron]
+        const int64_t r = e - (inf_copy ? L.off_o : L.off_f);
         const int s = (int)(r % M::EPL);
         const int lane = (int)((r / M::EPL) % 64);
         const int64_t fr = r / (M::EPL * 64);
         const int kc = (int)(fr % L.kc_in_f);
         const int ob = (int)(fr / L.kc_in_f);
-        const int row = 16 * ob + lane % 16;
+        const int row = inf_copy ? out_neuron(ob, lane % 16, L.gb_o) : 16 * ob + lane % 16;
         const int col = kperm<DT>(kc, lane / 16, s);
         if (row < L.out && col < L.in) v = W[(int64_t)row * L.in + col];
     } else {                                 // backward: A[row = in neuron][K = out neuron] = W^T
@@ -115,23 +125,132 @@ __device__ inline void mlp_layer(const typename Mma<DT>::elem* W, int lane, cons
     }
 }
 
-template <int NSUB, int NB>
+// Hidden activation in FP32: ReLU (a float with the sign bit set is a
+// negative int32, so max(bits, 0) is one instruction) or leaky ReLU with
+// 0 < slope <= 1.
+template <bool LEAKY, int NSUB, int NB>
 __device__ inline void activate(float (&a)[NSUB][NB][4], float slope) {
-    if (slope == 0.0f) {       // ReLU: a float with the sign bit set is a negative int32, so max(bits, 0) is one op
 #pragma unroll
-        for (int s = 0; s < NSUB; ++s)
+    for (int s = 0; s < NSUB; ++s)
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) a[s][b][i] = __int_as_float(max(__float_as_int(a[s][b][i]), 0));
-    } else {                   // leaky, 0 < slope <= 1
-#pragma unroll
-        for (int s = 0; s < NSUB; ++s)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) a[s][b][i] = fmaxf(a[s][b][i], slope * a[s][b][i]);
+            for (int i = 0; i < 4; ++i)
+                a[s][b][i] = LEAKY ? fmaxf(a[s][b][i], slope * a[s][b][i])
+                                   : __int_as_float(max(__float_as_int(a[s][b][i]), 0));
+}
+
+// Next layer's B fragment from the accumulators of output blocks 2c (lo) and
+// 2c+1 (hi), in kperm order, after the hidden activation.  The ReLU is taken
+// on the rounded 16-bit values as a packed integer max with zero: a negative
+// value (-0 included) has the sign bit set, so this equals rounding the FP32
+// ReLU, in one instruction per two neurons.
+template <int DT>
+__device__ inline typename Mma<DT>::frag frag_of(float4_t lo, float4_t hi) {
+    // Pairwise vector conversions: one packed convert per two neurons.
+    using E = typename Mma<DT>::elem;
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef E e2 __attribute__((ext_vector_type(2)));
+    const e2 p0 = __builtin_convertvector((f2){lo[0], lo[1]}, e2);
+    const e2 p1 = __builtin_convertvector((f2){lo[2], lo[3]}, e2);
+    const e2 p2 = __builtin_convertvector((f2){hi[0], hi[1]}, e2);
+    const e2 p3 = __builtin_convertvector((f2){hi[2], hi[3]}, e2);
+    return typename Mma<DT>::frag{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+}
+
+template <bool LEAKY, int DT>
+__device__ inline typename Mma<DT>::frag act_frag(float4_t lo, float4_t hi, float slope) {
+    if constexpr (!LEAKY) {
+        typedef short short8_t __attribute__((ext_vector_type(8)));
+        const short8_t b = __builtin_elementwise_max(__builtin_bit_cast(short8_t, frag_of<DT>(lo, hi)), (short8_t)0);
+        return __builtin_bit_cast(typename Mma<DT>::frag, b);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        lo[i] = fmaxf(lo[i], slope * lo[i]);
+        hi[i] = fmaxf(hi[i], slope * hi[i]);
+    }
+    return frag_of<DT>(lo, hi);
+}
+
+// 16-bit layers are software-pipelined over 16-neuron output blocks: the
+// weight fragments of block u+1 are read from LDS while the matrix cores work
+// on block u (a scheduling barrier keeps the reads ahead), and the finished
+// blocks are activated (or passed through the sigmoid and stored) under the
+// next block's matrix work.
+template <int DT, int KCI>
+__device__ inline void load_block(const typename Mma<DT>::elem* W, int ob, int lane,
+                                  typename Mma<DT>::frag (&w)[KCI]) {
+#pragma unroll
+    for (int kc = 0; kc < KCI; ++kc) w[kc] = load_frag<DT>(W, ob, kc, KCI, lane);
+}
+
+template <int DT, int NSUB, int KCI>
+__device__ inline void mma_block(const typename Mma<DT>::frag (&w)[KCI],
+                                 const typename Mma<DT>::frag (&in)[NSUB][KCI], float4_t (&acc)[NSUB]) {
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) acc[s] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KCI; ++kc)
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) acc[s] = Mma<DT>::mma(w[kc], in[s][kc], acc[s]);
+}
+
+// Hidden layer on 16-bit operands: the activations live in registers as the
+// next layer's B fragments (KCI input chunks, KCO output chunks per sub-tile).
+template <bool LEAKY, int DT, int NSUB, int KCI, int KCO>
+__device__ inline void hidden_layer16(const typename Mma<DT>::elem* W, int lane,
+                                      const typename Mma<DT>::frag (&in)[NSUB][KCI],
+                                      typename Mma<DT>::frag (&out)[NSUB][KCO], float slope) {
+    using FR = typename Mma<DT>::frag;
+    constexpr int U = 2 * KCO;
+    FR w[2][KCI];
+    float4_t acc[U][NSUB];
+    load_block<DT, KCI>(W, 0, lane, w[0]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (u + 1 < U) load_block<DT, KCI>(W, u + 1, lane, w[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_block<DT, NSUB, KCI>(w[u & 1], in, acc[u]);
+        if (u % 2 == 0 && u >= 2) {
+#pragma unroll
+            for (int s = 0; s < NSUB; ++s) out[s][u / 2 - 1] = act_frag<LEAKY, DT>(acc[u - 2][s], acc[u - 1][s], slope);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) out[s][KCO - 1] = act_frag<LEAKY, DT>(acc[U - 2][s], acc[U - 1][s], slope);
+}
+
+// Output layer on 16-bit operands.  The output blocks are taken GB at a
+// time (gb_o of the packing); emit(s, c, v) receives the 4*GB visibilities
+// that a lane holds for group c of sub-tile s, consecutive outputs in the
+// out_neuron row order.
+template <int DT, int NSUB, int KCI, int NBO, int GB, class Emit>
+__device__ inline void output_layer16(const typename Mma<DT>::elem* W, int lane,
+                                      const typename Mma<DT>::frag (&in)[NSUB][KCI], Emit&& emit) {
+    using FR = typename Mma<DT>::frag;
+    FR w[2][KCI];
+    float4_t acc[NBO][NSUB];
+    auto finish = [&](int c) {
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            float v[4 * GB];
+#pragma unroll
+            for (int j = 0; j < GB; ++j)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[4 * j + i] = sigmoid_fast(acc[GB * c + j][s][i]);
+            emit(s, c, v);
+        }
+    };
+    load_block<DT, KCI>(W, 0, lane, w[0]);
+#pragma unroll
+    for (int u = 0; u < NBO; ++u) {
+        if (u + 1 < NBO) load_block<DT, KCI>(W, u + 1, lane, w[(u + 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_block<DT, NSUB, KCI>(w[u & 1], in, acc[u]);
+        if (u % GB == 0 && u >= GB) finish(u / GB - 1);
+    }
+    finish(NBO / GB - 1);
 }
 
 // Fragments of the forward matrices, compact in LDS: layer 0, hidden layers, output layer.
@@ -160,64 +279,109 @@ struct InferArgs {
     int vis_dtype;
     int act;
     float slope;
-    int vec_ok;           // rows start 4-element aligned and vis is 16-byte aligned: vector stores
+    int vec_ok;           // n_out % 4 == 0 and vis 16-byte aligned: 4-output vector stores
+    int vec8_ok;          // n_out % 8 == 0 and vis 16-byte aligned: 8-output vector stores
     const void* enc;      // pre-computed encoding [n][n_in] (nvc_mlp_forward), else nullptr
     int enc_dtype;
     int n_in;
     int enc_vec;          // n_in % 4 == 0 and enc 16-byte aligned
 };
 
-// Encoding features of point p a lane owns (layout of encode_lane), read from
-// a pre-computed [n][n_in] buffer and rounded to FP32.  vec: n_in is a
-// multiple of 4 and the buffer 16-byte aligned, so a lane's four features of
-// a block are one aligned load.
+// Encoding words of point p that a lane owns (layout of encode_lane), as
+// loaded from a pre-computed [n][n_in] buffer.  vec: n_in is a multiple of 4
+// and the buffer 16-byte aligned, so a lane's four features of a block are
+// one aligned load (four FP32 words, or two words of 16-bit pairs); otherwise
+// one feature per word, zero past n_in.  Kept raw so that the load of the
+// next tile can be in flight while this one is computed.
 template <int NINB>
-__device__ inline void load_lane_encoding(const void* enc, int enc_dtype, int n_in, bool vec, int64_t p, int grp,
-                                          float (&act)[NINB][4]) {
+__device__ inline void load_enc_raw(const void* enc, int enc_dtype, int n_in, bool vec, int64_t p, int grp,
+                                    uint32_t (&raw)[NINB][4]) {
 #pragma unroll
     for (int b = 0; b < NINB; ++b) {
         const int f0 = 16 * b + 4 * grp;
         const int64_t o = p * n_in + f0;
         if (vec && f0 + 4 <= n_in) {
             if (enc_dtype == DT_F32) {
-                const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(enc) + o);
-                act[b][0] = v.x; act[b][1] = v.y; act[b][2] = v.z; act[b][3] = v.w;
-            } else if (enc_dtype == DT_F16) {
-                typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-                const h4 v = *reinterpret_cast<const h4*>(reinterpret_cast<const _Float16*>(enc) + o);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) act[b][i] = (float)v[i];
+                const uint4 v = *reinterpret_cast<const uint4*>(reinterpret_cast<const float*>(enc) + o);
+                raw[b][0] = v.x; raw[b][1] = v.y; raw[b][2] = v.z; raw[b][3] = v.w;
             } else {
-                typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-                const b4 v = *reinterpret_cast<const b4*>(reinterpret_cast<const __bf16*>(enc) + o);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) act[b][i] = (float)v[i];
+                const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(enc) + o);
+                raw[b][0] = v.x; raw[b][1] = v.y; raw[b][2] = 0; raw[b][3] = 0;
             }
         } else {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float v = 0.0f;
-                if (f0 + i < n_in) {
-                    if (enc_dtype == DT_F32)
-                        v = reinterpret_cast<const float*>(enc)[o + i];
-                    else if (enc_dtype == DT_F16)
-                        v = (float)reinterpret_cast<const _Float16*>(enc)[o + i];
-                    else
-                        v = (float)reinterpret_cast<const __bf16*>(enc)[o + i];
-                }
-                act[b][i] = v;
+                uint32_t w = 0;
+                if (f0 + i < n_in)
+                    w = enc_dtype == DT_F32 ? reinterpret_cast<const uint32_t*>(enc)[o + i]
+                                            : (uint32_t)reinterpret_cast<const uint16_t*>(enc)[o + i];
+                raw[b][i] = w;
             }
         }
     }
 }
 
-// Waves per block: eight for the 128-wide network (twelve when the encoding
-// is read from memory: fewer registers), whose weights fill most of the LDS
-// (one block per CU); four otherwise.
-template <class C, bool PRE> constexpr int infer_waves() { return C::WB >= 8 ? (PRE ? 12 : 8) : 4; }
+// The features of load_enc_raw's words, rounded to FP32.
+template <int NINB>
+__device__ inline void decode_enc(int enc_dtype, int n_in, bool vec, int grp, const uint32_t (&raw)[NINB][4],
+                                  float (&act)[NINB][4]) {
+#pragma unroll
+    for (int b = 0; b < NINB; ++b) {
+        const bool pairs = vec && 16 * b + 4 * grp + 4 <= n_in;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t h = (pairs ? raw[b][i / 2] >> (16 * (i % 2)) : raw[b][i]) & 0xffffu;
+            act[b][i] = enc_dtype == DT_F32 ? __uint_as_float(raw[b][i])
+                      : enc_dtype == DT_F16 ? (float)__builtin_bit_cast(_Float16, (uint16_t)h)
+                                            : __uint_as_float(h << 16);
+        }
+    }
+}
+
+// Visibilities v[0..N-1] of lights l0..l0+N-1 (N = 4 or 8) at point p, in
+// the output dtype.
+template <int N>
+__device__ inline void store_vis(const InferArgs& a, int64_t p, int l0, const float (&v)[N]) {
+    const int64_t base = p * a.n_out + l0;
+    const bool vec = (N == 4 ? a.vec_ok : a.vec8_ok) && l0 + N <= a.n_out;
+    if (vec && a.vis_dtype == DT_F32) {
+#pragma unroll
+        for (int q = 0; q < N; q += 4)
+            *reinterpret_cast<float4*>((float*)a.vis + base + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+    } else if (vec && a.vis_dtype == DT_F16) {
+        typedef _Float16 hN __attribute__((ext_vector_type(N)));
+        hN o;
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] = (_Float16)v[i];
+        *reinterpret_cast<hN*>((_Float16*)a.vis + base) = o;
+    } else if (vec) {
+        typedef __bf16 bN __attribute__((ext_vector_type(N)));
+        bN o;
+#pragma unroll
+        for (int i = 0; i < N; ++i) o[i] = (__bf16)v[i];
+        *reinterpret_cast<bN*>((__bf16*)a.vis + base) = o;
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            if (l0 + i >= a.n_out) break;
+            if (a.vis_dtype == DT_F32)
+                ((float*)a.vis)[base + i] = v[i];
+            else if (a.vis_dtype == DT_F16)
+                ((_Float16*)a.vis)[base + i] = (_Float16)v[i];
+            else
+                ((__bf16*)a.vis)[base + i] = (__bf16)v[i];
+        }
+    }
+}
+
+// Waves per block: twelve (three per SIMD) for the 128-wide network, whose
+// weights fill most of the LDS (one block per CU); four otherwise (several
+// blocks per CU).
+template <class C, bool PRE> constexpr int infer_waves() { return C::WB >= 8 ? 12 : 4; }
 
 // PRE: the encoding comes from a.enc (nvc_mlp_forward) instead of the table.
-template <class C, bool PRE>
+// LEAKY: leaky ReLU hidden activation, else ReLU.
+template <class C, bool PRE, bool LEAKY>
 __global__ __launch_bounds__((64 * infer_waves<C, PRE>())) void infer_kernel(InferArgs a) {
     constexpr int DT = C::DT;
     using M = Mma<DT>;
@@ -269,7 +433,43 @@ __global__ __launch_bounds__((64 * infer_waves<C, PRE>())) void infer_kernel(Inf
 
     LevelLane lv[C::NINB][4 / C::F];
     if constexpr (!PRE) lane_levels<C::F, C::NINB>(a.g, grp, lv);
-    for (int64_t t = t0 + wave; t < t1; t += infer_waves<C, PRE>()) {
+
+    // Output blocks per store group (gb_o of the packing).
+    constexpr int GB = (DT != DT_F32 && C::NOUTB % 2 == 0) ? 2 : 1;
+    constexpr int IW = infer_waves<C, PRE>();
+
+    // The inputs of the wave's next tile are fetched one iteration ahead, so
+    // that their memory latency is spent under this tile's matrix work: the
+    // raw encoding words (PRE) or the positions.
+    uint32_t raw[NSUB][C::NINB][4];
+    float px[NSUB][3];
+    auto fetch = [&](int64_t tt) {
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            const int64_t p = tt * PTS + s * 16 + col;
+            const int64_t pc = p < a.n ? p : a.n - 1;
+            if constexpr (PRE) {
+                load_enc_raw<C::NINB>(a.enc, a.enc_dtype, a.n_in, a.enc_vec != 0, pc, grp, raw[s]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) px[s][k] = a.pos[pc * 3 + k];
+            }
+        }
+    };
+    // This tile's encoding from the fetched inputs; then the next fetch.
+    auto stage = [&](int64_t t, float (&h0)[NSUB][C::NINB][4]) {
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            if constexpr (PRE)
+                decode_enc<C::NINB>(a.enc_dtype, a.n_in, a.enc_vec != 0, grp, raw[s], h0[s]);
+            else
+                encode_lane_lv<C::F, C::NINB>(a.table, lv, clamp_unit(px[s][0]), clamp_unit(px[s][1]),
+                                              clamp_unit(px[s][2]), h0[s]);
+        }
+        if (t + IW < t1) fetch(t + IW);
+    };
+    if (t0 + wave < t1) fetch(t0 + wave);
+    for (int64_t t = t0 + wave; t < t1; t += IW) {
         // Weight fragments are read from LDS (or L1) in every iteration: the
         // opaque zero offset stops the compiler from hoisting all of them into
         // registers, which would cost occupancy.
@@ -278,73 +478,67 @@ __global__ __launch_bounds__((64 * infer_waves<C, PRE>())) void infer_kernel(Inf
         const E* w_it[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) w_it[k] = wk[k] + opq;
-        float h0[NSUB][C::NINB][4];
+        if constexpr (DT != DT_F32) {
+            using FR = typename M::frag;
+            constexpr int KC0 = kchunks<DT>(C::NINB), KCW = kchunks<DT>(C::WB);
+            FR x0[NSUB][KC0];
+            {
+                float h0[NSUB][C::NINB][4];
+                stage(t, h0);
 #pragma unroll
-        for (int s = 0; s < NSUB; ++s) {
-            const int64_t p = t * PTS + s * 16 + col;
-            const int64_t pc = p < a.n ? p : a.n - 1;
-            if constexpr (PRE) {
-                load_lane_encoding<C::NINB>(a.enc, a.enc_dtype, a.n_in, a.enc_vec != 0, pc, grp, h0[s]);
-            } else {
-                const float x = clamp_unit(a.pos[pc * 3 + 0]);
-                const float y = clamp_unit(a.pos[pc * 3 + 1]);
-                const float z = clamp_unit(a.pos[pc * 3 + 2]);
-                encode_lane_lv<C::F, C::NINB>(a.table, lv, x, y, z, h0[s]);
-            }
-        }
-        float ha[NSUB][C::WB][4], hb[NSUB][C::WB][4];
-        mlp_layer<DT, NSUB, C::NINB, C::WB>(w_it[0], lane, h0, ha);
-        activate<NSUB, C::WB>(ha, a.slope);
+                for (int s = 0; s < NSUB; ++s)
 #pragma unroll
-        for (int k = 1; k < C::NHID; ++k) {
-            if (k % 2 == 1) {
-                mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, ha, hb);
-                activate<NSUB, C::WB>(hb, a.slope);
-            } else {
-                mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, hb, ha);
-                activate<NSUB, C::WB>(ha, a.slope);
+                    for (int kc = 0; kc < KC0; ++kc) x0[s][kc] = make_frag<DT, C::NINB>(h0[s], kc);
             }
-        }
-        float z[NSUB][C::NOUTB][4];
-        if (C::NHID % 2 == 1)
-            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, ha, z);
-        else
-            mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, hb, z);
+            FR xa[NSUB][KCW], xb[NSUB][KCW];
+            hidden_layer16<LEAKY, DT, NSUB, KC0, KCW>(w_it[0], lane, x0, xa, a.slope);
+#pragma unroll
+            for (int k = 1; k < C::NHID; ++k) {
+                if (k % 2 == 1)
+                    hidden_layer16<LEAKY, DT, NSUB, KCW, KCW>(w_it[k], lane, xa, xb, a.slope);
+                else
+                    hidden_layer16<LEAKY, DT, NSUB, KCW, KCW>(w_it[k], lane, xb, xa, a.slope);
+            }
+            auto emit = [&](int s, int c, const float (&v)[4 * GB]) {
+                const int64_t p = t * PTS + s * 16 + col;
+                if (p < a.n) store_vis<4 * GB>(a, p, 16 * GB * c + 4 * GB * grp, v);
+            };
+            if constexpr (C::NHID % 2 == 1)
+                output_layer16<DT, NSUB, KCW, C::NOUTB, GB>(w_it[NL - 1], lane, xa, emit);
+            else
+                output_layer16<DT, NSUB, KCW, C::NOUTB, GB>(w_it[NL - 1], lane, xb, emit);
+        } else {   // FP32 matrix cores: activations in FP32 registers
+            float h0[NSUB][C::NINB][4];
+            stage(t, h0);
+            float ha[NSUB][C::WB][4], hb[NSUB][C::WB][4];
+            mlp_layer<DT, NSUB, C::NINB, C::WB>(w_it[0], lane, h0, ha);
+            activate<LEAKY, NSUB, C::WB>(ha, a.slope);
+#pragma unroll
+            for (int k = 1; k < C::NHID; ++k) {
+                if (k % 2 == 1) {
+                    mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, ha, hb);
+                    activate<LEAKY, NSUB, C::WB>(hb, a.slope);
+                } else {
+                    mlp_layer<DT, NSUB, C::WB, C::WB>(w_it[k], lane, hb, ha);
+                    activate<LEAKY, NSUB, C::WB>(ha, a.slope);
+                }
+            }
+            float z[NSUB][C::NOUTB][4];
+            if (C::NHID % 2 == 1)
+                mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, ha, z);
+            else
+                mlp_layer<DT, NSUB, C::WB, C::NOUTB>(w_it[NL - 1], lane, hb, z);
 
 #pragma unroll
-        for (int s = 0; s < NSUB; ++s) {
-            const int64_t p = t * PTS + s * 16 + col;
-            if (p >= a.n) continue;
+            for (int s = 0; s < NSUB; ++s) {
+                const int64_t p = t * PTS + s * 16 + col;
+                if (p >= a.n) continue;
 #pragma unroll
-            for (int ob = 0; ob < C::NOUTB; ++ob) {
-                const int l0 = 16 * ob + 4 * grp;
-                float v[4];
+                for (int ob = 0; ob < C::NOUTB; ++ob) {
+                    float v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = sigmoid_fast(z[s][ob][i]);
-                const int64_t base = p * a.n_out + l0;
-                if (a.vec_ok && l0 + 4 <= a.n_out) {
-                    if (a.vis_dtype == DT_F32) {
-                        *reinterpret_cast<float4*>((float*)a.vis + base) = make_float4(v[0], v[1], v[2], v[3]);
-                    } else if (a.vis_dtype == DT_F16) {
-                        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-                        h4 o = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-                        *reinterpret_cast<h4*>((_Float16*)a.vis + base) = o;
-                    } else {
-                        typedef __bf16 b4 __attribute__((ext_vector_type(4)));
-                        b4 o = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-                        *reinterpret_cast<b4*>((__bf16*)a.vis + base) = o;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (l0 + i >= a.n_out) break;
-                        if (a.vis_dtype == DT_F32)
-                            ((float*)a.vis)[base + i] = v[i];
-                        else if (a.vis_dtype == DT_F16)
-                            ((_Float16*)a.vis)[base + i] = (_Float16)v[i];
-                        else
-                            ((__bf16*)a.vis)[base + i] = (__bf16)v[i];
-                    }
+                    for (int i = 0; i < 4; ++i) v[i] = sigmoid_fast(z[s][ob][i]);
+                    store_vis<4>(a, p, 16 * ob + 4 * grp, v);
                 }
             }
         }
@@ -377,6 +571,9 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     a.table = table;
     a.packed = packed;
     for (int k = 0; k < plan.n_layers; ++k) a.layer_off[k] = plan.layer[k].off_f;
+    a.layer_off[plan.n_layers - 1] = plan.layer[plan.n_layers - 1].off_o;
+    if (plan.layer[plan.n_layers - 1].gb_o != ((C::DT != DT_F32 && C::NOUTB % 2 == 0) ? 2 : 1))
+        return hipErrorInvalidValue;
     a.pos = pos;
     a.n = n;
     a.n_out = n_out;
@@ -385,6 +582,7 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     a.act = act;
     a.slope = slope;
     a.vec_ok = (n_out % 4) == 0 && ((uintptr_t)vis % 16) == 0;
+    a.vec8_ok = (n_out % 8) == 0 && ((uintptr_t)vis % 16) == 0;
     using LY = FwdLayout<C>;
     const size_t wbytes = (size_t)LY::total * sizeof(typename Mma<C::DT>::elem);
     const size_t smem = wbytes <= (size_t)kInferLdsMax ? wbytes : 0;
@@ -395,10 +593,15 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     int64_t want = (ntiles + IW - 1) / IW;                  // at least one tile per wave
     int64_t G = std::min<int64_t>(want, (int64_t)cu_count() * per_cu);
     G = std::max<int64_t>(8, (G + 7) / 8 * 8);
-    if (enc)
-        hipLaunchKernelGGL((infer_kernel<C, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+    const bool leaky = slope != 0.0f;
+    if (enc && leaky)
+        hipLaunchKernelGGL((infer_kernel<C, true, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+    else if (enc)
+        hipLaunchKernelGGL((infer_kernel<C, true, false>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+    else if (leaky)
+        hipLaunchKernelGGL((infer_kernel<C, false, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
     else
-        hipLaunchKernelGGL((infer_kernel<C, false>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+        hipLaunchKernelGGL((infer_kernel<C, false, false>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
     return hipGetLastError();
 }
 

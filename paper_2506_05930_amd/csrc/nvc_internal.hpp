@@ -30,14 +30,27 @@ struct NetShape {
     float slope;
 };
 
-// Packed-weight layout: per layer, the forward fragments then the transposed ones.
+// Packed-weight layout: per layer, the forward fragments then the transposed
+// ones; after the output layer's, a copy of its forward fragments with the
+// rows in the inference kernel's store order (out_neuron, gb_o = 2), or
+// off_o = off_f when that order is the natural one (gb_o = 1).
 struct LayerPack {
     int in, out;              // logical sizes
     int nb_out_f, kc_in_f;    // forward: 16-row blocks of `out`, K-chunks over `in`
     int nb_in_b, kc_out_b;    // backward: 16-row blocks of `in`, K-chunks over `out`
     int64_t off_f, off_b;     // element offsets into the packed buffer
+    int64_t off_o;            // forward fragments in inference row order
+    int gb_o;                 // output blocks per store group of the inference kernel
     int64_t w_off;            // float offset of this layer in the master weights
 };
+
+// Output neuron held in row r (0..15) of forward block ob for store groups of
+// gb blocks.  gb = 2: a 16x16 matrix-core result gives lane group g = r/4 the
+// rows 4g..4g+3 of a block, so group g of the block pair (2c, 2c+1) holds the
+// eight consecutive neurons 32c + 8g + [0, 8).
+__host__ __device__ constexpr int out_neuron(int ob, int r, int gb) {
+    return gb == 2 ? 32 * (ob / 2) + 8 * (r / 4) + 4 * (ob % 2) + (r % 4) : 16 * ob + r;
+}
 
 constexpr int kMaxLayers = 8;
 
