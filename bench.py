@@ -63,9 +63,13 @@ def algorithmic(wl, n_pix, batch):
     L, F, M = wl.grid.n_levels, wl.grid.n_feat, wl.mlp.n_out
     n_params = wl.grid.n_params + wl.mlp.n_params
     vis_b = 2 if wl.mlp.dtype != "f32" else 4
+    # 8 corners x F x 4 B per level per query; a table that fits in the L2 (8 XCDs x 4 MiB) is read from
+    # HBM once per launch instead
+    table_b = wl.grid.n_params * 4
+    gathers = n_pix * L * 8 * F * 4 if table_b > L2_BYTES else table_b
     return {
-        # 12 B position + 8 corners x F x 4 B per level + M visibilities out
-        "infer": {"bytes": n_pix * (12 + L * 8 * F * 4 + M * vis_b), "flops": n_pix * wl.mlp.flops_per_point},
+        # 12 B position + gathers + M visibilities out
+        "infer": {"bytes": n_pix * (12 + M * vis_b) + gathers, "flops": n_pix * wl.mlp.flops_per_point},
         # visibilities + position + normal in, index/pmf/W/DI out
         "wrs": {"bytes": n_pix * (M * vis_b + 24 + 16)},
         "pixels": {"bytes": batch * 4},
@@ -92,18 +96,19 @@ def cpu_baseline(wl, scene, params, sample_pix: int):
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         vis = pipeline.infer(scene["pos_unit"][sel], params["table"], params["weights"], wl.grid.base_res,
-                             wl.grid.growth)
+                             wl.grid.growth, act=wl.mlp.act, slope=wl.mlp.leaky_slope)
         pipeline.sample(vis, scene["pos"][sel], scene["nrm"][sel], scene["lights"], wl.rng_key, 0, wl.vis_floor)
         t1 = time.perf_counter()
         pix = philox.training_pixels(wl.rng_key, 0, batch_s, n_pix)
         y = shadow.labels_fp32(scene["pos"][pix], scene["lights"], scene["spheres"])
         g = training.train_gradients(scene["pos_unit"][pix], params["table"], params["weights"], wl.grid.base_res,
-                                     wl.grid.growth, labels=y, loss=wl.loss)
+                                     wl.grid.growth, labels=y, loss=wl.loss, act=wl.mlp.act, slope=wl.mlp.leaky_slope)
         t2 = time.perf_counter()
-        n_adam = 1 << 20
+        n_adam = min(1 << 20, params["table"].size)
         z = np.zeros(n_adam)
         training.adam_step(params["table"].reshape(-1)[:n_adam], g["g_table"].reshape(-1)[:n_adam], z, z, 1,
-                           wl.lr, wl.beta1, wl.beta2, wl.adam_eps)
+                           training.learning_rate(1, wl.lr, wl.lr_end, wl.lr_decay_steps), wl.beta1, wl.beta2,
+                           wl.adam_eps)
         t3 = time.perf_counter()
     frame_s = ((t1 - t0) * n_pix / sample_pix + (t2 - t1) * wl.train_batch / batch_s
                + (t3 - t2) * (wl.grid.n_params + wl.mlp.n_params) / n_adam)
@@ -164,6 +169,8 @@ def estimator_stats(f, V, v, floor):
         out[name] = {"var": float(var[ok].mean()), "p_occluded": float((p * (V == 0)).sum(1)[ok].mean())}
     return out
 
+
+L2_BYTES = 8 * 4 * 1024 * 1024
 
 PEAK_MFMA_TFLOPS = {"f16": 2500.0, "bf16": 2500.0, "f32": 157.3}
 
@@ -273,12 +280,12 @@ def main():
     wl = get_workload(args.workload, **over)
     dev = torch.device("cuda:0")
     scene = box_scene(wl.scene_seed, wl.width, wl.height, wl.n_boxes, wl.n_lights, wl.n_spheres)
-    params = init_params(wl.init_seed, wl.grid, wl.mlp)
+    params = init_params(wl.init_seed, wl.grid, wl.mlp, init=wl.init)
     n_pix = wl.width * wl.height
     B = wl.train_batch
     cache = NVCache(wl.grid, wl.mlp, params["table"], params["weights"], device=dev, seed=wl.rng_key, lr=wl.lr,
                     beta1=wl.beta1, beta2=wl.beta2, eps=wl.adam_eps, loss=wl.loss, vis_floor=wl.vis_floor,
-                    max_batch=B)
+                    max_batch=B, lr_end=wl.lr_end, lr_decay_steps=wl.lr_decay_steps)
     pos_unit = torch.as_tensor(scene["pos_unit"]).to(dev)
     pos = torch.as_tensor(scene["pos"]).to(dev)
     nrm = torch.as_tensor(scene["nrm"]).to(dev)

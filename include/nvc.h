@@ -236,14 +236,20 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
 
 /* One Adam step (Sec. 3.4; Kingma & Ba) over `count` FP32 parameters, dense:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
- *   p -= (lr / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)
+ *   p -= (lr_t / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)
  * step >= 1 counts from 1 (with ctr: ctr->step at run time, values below 1
- * taken as 1).  The bias corrections are computed on the device in FP32:
- * b^step by repeated squaring, then a correctly rounded division and square
- * root.  If zero_grad != 0, g is set to 0 afterwards (the next
- * nvc_train_step then accumulates into a clean buffer). */
+ * taken as 1).  The learning rate lr_t is lr, or with lr_decay_steps = D > 0
+ * the schedule of Sec. 3.4 (a rate lowered linearly over the first training
+ * steps): with f = min(step - 1, D) / D, lr_t = (1 - f) lr + f lr_end, from lr
+ * at step 1 to lr_end at step D + 1 and after.  The rate and the bias corrections are
+ * computed on the device in FP32: b^step by repeated squaring, then correctly
+ * rounded divisions and square root.  If zero_grad != 0, g is set to 0
+ * afterwards (the next nvc_train_step then accumulates into a clean buffer).
+ * lr, lr_end and eps must be finite and >= 0, lr_decay_steps >= 0, betas in
+ * [0, 1) (else NVC_ERR_SHAPE). */
 int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, const nvc_counters* ctr,
-             float lr, float beta1, float beta2, float eps, int32_t zero_grad, void* stream);
+             float lr, float lr_end, int32_t lr_decay_steps, float beta1, float beta2, float eps,
+             int32_t zero_grad, void* stream);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,11 @@ Adam (Kingma & Ba 2015) with bias correction, step t counted from 1, every
 parameter updated each step (dense), no weight decay:
     m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
     theta <- theta - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+
+Learning rate (Sec. 3.4): the paper starts at 0.05 and lowers the rate
+linearly over the first 200 steps to 0.001.  Reading: with f = min(t - 1,
+D) / D, lr_t = (1 - f) lr0 + f lr1, i.e. lr0 at step 1 and lr1 from step
+D + 1 on.
 """
 from __future__ import annotations
 
@@ -80,6 +85,14 @@ def train_gradients(pos32, table, weights, base_res, growth, labels=None, dvis=N
     g_w, d_enc = mlp.backward(weights, pre, inputs, dz, act, slope)
     g_table = table_gradient(d_enc, cache, table.shape)
     return {"loss": lval, "z": z, "g_table": g_table, "g_w": g_w, "d_enc": d_enc}
+
+
+def learning_rate(t: int, lr0: float, lr1: float | None = None, decay_steps: int = 0) -> float:
+    """Rate of step t >= 1 (FP64): lr0, or the linear decay to lr1 over decay_steps steps (Sec. 3.4)."""
+    if decay_steps <= 0 or lr1 is None:
+        return float(lr0)
+    f = min(t - 1, decay_steps) / decay_steps
+    return (1.0 - f) * float(lr0) + f * float(lr1)
 
 
 def adam_step(p, g, m, v, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8):

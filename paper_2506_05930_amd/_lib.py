@@ -70,7 +70,7 @@ _SIGS = {
                                  c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int64, c_void_p]),
     "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_float, c_float,
-                           c_float, c_float, c_int32, c_void_p]),
+                           c_int32, c_float, c_float, c_float, c_int32, c_void_p]),
     "nvc_counters_advance": (c_int32, [c_void_p, c_void_p]),
 }
 

@@ -213,10 +213,14 @@ def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torc
 
 
 def nvc_adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
-             beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None, ctr=None) -> None:
+             beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None, ctr=None,
+             lr_end: float | None = None, lr_decay_steps: int = 0) -> None:
+    """lr_end / lr_decay_steps: the rate falls linearly from lr to lr_end over lr_decay_steps steps (0: constant)."""
     n = p.numel()
     ptrs = [_ptr(t, name, torch.float32) for t, name in ((p, "p"), (g, "g"), (m, "m"), (v, "v"))]
     if any(t.numel() != n for t in (g, m, v)):
         raise ValueError("p, g, m, v must have the same number of elements")
-    _lib.check("nvc_adam", _lib.load().nvc_adam(*ptrs, n, int(step), _counters(ctr), float(lr), float(beta1), float(beta2),
-                                                float(eps), int(bool(zero_grad)), _stream(stream)))
+    _lib.check("nvc_adam", _lib.load().nvc_adam(*ptrs, n, int(step), _counters(ctr), float(lr),
+                                                float(lr if lr_end is None else lr_end), int(lr_decay_steps),
+                                                float(beta1), float(beta2), float(eps), int(bool(zero_grad)),
+                                                _stream(stream)))

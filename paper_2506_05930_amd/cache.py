@@ -27,7 +27,7 @@ from ._lib import NVC_LOSS_BCE, NVC_LOSS_L2
 class NVCache:
     def __init__(self, grid_cfg, mlp_cfg, table, weights, device="cuda", seed: int = 2, lr: float = 1e-2,
                  beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8, loss: str = "bce",
-                 vis_floor: float = 1e-3, max_batch: int = 0):
+                 vis_floor: float = 1e-3, max_batch: int = 0, lr_end: float | None = None, lr_decay_steps: int = 0):
         self.grid = api.make_grid(grid_cfg.n_levels, grid_cfg.n_feat, grid_cfg.log2_T, grid_cfg.base_res,
                                   grid_cfg.growth)
         self.mlp = api.make_mlp(mlp_cfg.n_in, mlp_cfg.width, mlp_cfg.n_hidden, mlp_cfg.n_out, mlp_cfg.act,
@@ -36,6 +36,7 @@ class NVCache:
         self.vis_dtype = api.torch_dtype(self.mlp.dtype)
         self.seed = int(seed)
         self.lr, self.beta1, self.beta2, self.eps = lr, beta1, beta2, eps
+        self.lr_end, self.lr_decay_steps = lr_end, lr_decay_steps     # linear decay of Sec. 3.4 (0: constant)
         self.loss = {"bce": NVC_LOSS_BCE, "l2": NVC_LOSS_L2}[loss]
         self.vis_floor = vis_floor
         self.table = torch.as_tensor(np.ascontiguousarray(table), dtype=torch.float32).to(self.device)
@@ -119,7 +120,8 @@ class NVCache:
         if ctr is None:
             self.step += 1
         for p, g, m, v in ((self.table, self.g_table, self.m_table, self.v_table), (self.w, self.g_w, self.m_w, self.v_w)):
-            api.nvc_adam(p, g, m, v, self.step, self.lr, self.beta1, self.beta2, self.eps, True, stream, ctr=ctr)
+            api.nvc_adam(p, g, m, v, self.step, self.lr, self.beta1, self.beta2, self.eps, True, stream, ctr=ctr,
+                         lr_end=self.lr_end, lr_decay_steps=self.lr_decay_steps)
         self.pack(stream)
 
     def train_gradients(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int,

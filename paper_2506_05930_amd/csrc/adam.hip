@@ -26,13 +26,22 @@ __device__ inline float pow_steps(float b, int t) {
     return r;
 }
 
+// Learning rate of step t >= 1: lr, or lowered linearly to lr_end over the
+// first `decay` steps (Sec. 3.4), in FP32.
+__device__ inline float scheduled_lr(float lr, float lr_end, int decay, int t) {
+    if (decay <= 0) return lr;
+    const float frac = __fdiv_rn((float)min(t - 1, decay), (float)decay);
+    return (1.0f - frac) * lr + frac * lr_end;
+}
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                                                    float* __restrict__ v, int64_t count, int step,
-                                                   const int32_t* __restrict__ step_dev, float lr, float b1, float b2,
-                                                   float eps, int zero_grad, int aligned) {
+                                                   const int32_t* __restrict__ step_dev, float lr, float lr_end,
+                                                   int decay, float b1, float b2, float eps, int zero_grad,
+                                                   int aligned) {
     int t = step_dev ? *step_dev : step;
     if (t < 1) t = 1;
-    const float step_size = __fdiv_rn(lr, 1.0f - pow_steps(b1, t));
+    const float step_size = __fdiv_rn(scheduled_lr(lr, lr_end, decay, t), 1.0f - pow_steps(b1, t));
     const float bc2_sqrt = sqrt_rn(1.0f - pow_steps(b2, t));
     const int64_t n4 = aligned ? count / 4 : 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -66,15 +75,16 @@ __global__ void counters_advance_kernel(uint32_t* frame_dev, int32_t* step_dev) 
 int cu_count();
 
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
-                       float lr, float beta1, float beta2, float eps, int zero_grad, hipStream_t st) {
+                       float lr, float lr_end, int lr_decay_steps, float beta1, float beta2, float eps, int zero_grad,
+                       hipStream_t st) {
     const int64_t n4 = (count + 3) / 4;
     int64_t blocks = (n4 + 255) / 256;
     const int64_t cap = (int64_t)cu_count() * 8;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     const int aligned = (((uintptr_t)p | (uintptr_t)g | (uintptr_t)m | (uintptr_t)v) & 15u) == 0;
-    adam_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, count, step, step_dev, lr, beta1, beta2, eps,
-                                                 zero_grad, aligned);
+    adam_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, count, step, step_dev, lr, lr_end, lr_decay_steps,
+                                                 beta1, beta2, eps, zero_grad, aligned);
     return hipGetLastError();
 }
 

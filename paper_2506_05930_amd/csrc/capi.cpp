@@ -236,14 +236,16 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
 }
 
 int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, const nvc_counters* ctr, float lr,
-             float beta1, float beta2, float eps, int32_t zero_grad, void* stream) {
-    if (count < 0 || (!ctr && step < 1)) return NVC_ERR_SHAPE;
+             float lr_end, int32_t lr_decay_steps, float beta1, float beta2, float eps, int32_t zero_grad,
+             void* stream) {
+    if (count < 0 || (!ctr && step < 1) || lr_decay_steps < 0) return NVC_ERR_SHAPE;
     if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f)) return NVC_ERR_SHAPE;
     if (!(lr >= 0.0f) || !isfinite(lr) || !(eps >= 0.0f) || !isfinite(eps)) return NVC_ERR_SHAPE;
+    if (!(lr_end >= 0.0f) || !isfinite(lr_end)) return NVC_ERR_SHAPE;
     if (count == 0) return NVC_OK;
     if (!p || !g || !m || !v) return NVC_ERR_NULL;
-    return hip_status(launch_adam(p, g, m, v, count, step, ctr ? &ctr->step : nullptr, lr, beta1, beta2, eps,
-                                  zero_grad, (hipStream_t)stream));
+    return hip_status(launch_adam(p, g, m, v, count, step, ctr ? &ctr->step : nullptr, lr, lr_end, lr_decay_steps,
+                                  beta1, beta2, eps, zero_grad, (hipStream_t)stream));
 }
 
 int nvc_counters_advance(nvc_counters* ctr, void* stream) {

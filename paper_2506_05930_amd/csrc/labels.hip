@@ -138,10 +138,14 @@ __device__ inline uint32_t spread10(uint32_t v) {        // 10 bits -> every thi
     return v;
 }
 
-constexpr int kLabelBlock = 1024;   // samples per block (16 waves of 64)
-constexpr int kLabelLights = 8;     // lights per block (grid.y covers all lights)
+int cu_count();
 
-// Block (x, y): samples [x*1024, x*1024 + 1024) and lights [8y, 8y + 8).  The
+constexpr int kLabelBlock = 1024;   // samples per block (16 waves of 64)
+constexpr int kLabelLights = 8;     // most lights per block (grid.y covers all lights)
+
+// Block (x, y): samples [x*1024, x*1024 + 1024) and lights [lpb*y, lpb*y + lpb),
+// lpb <= 8 lights per block (fewer when the batch is small, so that the grid
+// still covers the chip).  The
 // block sorts its samples by the 3D Morton code of their position inside the
 // block's bounding box, so each wave of 64 consecutive sorted samples is
 // compact in space (samples on both sides of a depth edge go to different
@@ -149,16 +153,16 @@ constexpr int kLabelLights = 8;     // lights per block (grid.y covers all light
 __global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ pos, const int32_t* __restrict__ pix,
                                                       int64_t n, const float* __restrict__ lights, int m,
                                                       const float* __restrict__ spheres, int n_spheres,
-                                                      uint8_t* __restrict__ labels) {
+                                                      uint8_t* __restrict__ labels, int lpb) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
     float4* S = reinterpret_cast<float4*>(smem_raw);                          // (cx, cy, cz, r*r)
     float* R = reinterpret_cast<float*>(S + n_spheres);                       // r
     float4* Lg = reinterpret_cast<float4*>(R + ((n_spheres + 3) & ~3));       // this block's lights
-    uint32_t* inside = reinterpret_cast<uint32_t*>(Lg + kLabelLights);        // [n_spheres]: bit i = light 8y+i
+    uint32_t* inside = reinterpret_cast<uint32_t*>(Lg + kLabelLights);        // [n_spheres]: bit i = light l0+i
     __shared__ uint64_t keys[kLabelBlock];
     __shared__ uint32_t scale_bits;
-    const int l0 = blockIdx.y * kLabelLights;
-    const int nl = min(kLabelLights, m - l0);
+    const int l0 = blockIdx.y * lpb;
+    const int nl = min(lpb, m - l0);
     if (threadIdx.x == 0) scale_bits = 0;
     __syncthreads();
     uint32_t my_scale = 0;
@@ -364,9 +368,13 @@ size_t labels_smem_bytes(int m, int n_spheres) {
 hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
                          const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st) {
     const size_t smem = labels_smem_bytes(m, n_spheres);
-    const dim3 grid((unsigned)((n + kLabelBlock - 1) / kLabelBlock), (unsigned)((m + kLabelLights - 1) / kLabelLights));
+    const int64_t bx = (n + kLabelBlock - 1) / kLabelBlock;
+    // Eight lights per block unless that leaves fewer than two blocks per CU.
+    int lpb = kLabelLights;
+    while (lpb > 1 && bx * ((m + lpb - 1) / lpb) < 2 * (int64_t)cu_count()) lpb >>= 1;
+    const dim3 grid((unsigned)bx, (unsigned)((m + lpb - 1) / lpb));
     hipLaunchKernelGGL(labels_kernel, grid, dim3(kLabelBlock), smem, st, pos, pix, n, lights, m, spheres, n_spheres,
-                       labels);
+                       labels, lpb);
     return hipGetLastError();
 }
 

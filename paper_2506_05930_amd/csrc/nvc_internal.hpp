@@ -90,7 +90,8 @@ hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& pl
                         const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
                         float* g_w, float* loss_out, void* workspace, hipStream_t st);
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
-                       float lr, float beta1, float beta2, float eps, int zero_grad, hipStream_t st);
+                       float lr, float lr_end, int lr_decay_steps, float beta1, float beta2, float eps, int zero_grad,
+                       hipStream_t st);
 // frame += 1, step += 1 of the device counters {uint32 frame; int32 step}.
 hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st);
 

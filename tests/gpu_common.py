@@ -25,7 +25,8 @@ def make_cache(wl, p, dtype=None, device="cuda", **kw):
     from paper_2506_05930_amd.cache import NVCache
     mlp = wl.mlp if dtype is None else replace(wl.mlp, dtype=dtype)
     return NVCache(wl.grid, mlp, p["table"], p["weights"], device=device, seed=wl.rng_key, lr=wl.lr,
-                   beta1=wl.beta1, beta2=wl.beta2, eps=wl.adam_eps, loss=wl.loss, vis_floor=wl.vis_floor, **kw)
+                   beta1=wl.beta1, beta2=wl.beta2, eps=wl.adam_eps, loss=wl.loss, vis_floor=wl.vis_floor,
+                   lr_end=wl.lr_end, lr_decay_steps=wl.lr_decay_steps, **kw)
 
 
 def rand_pos(seed, n, adversarial=True):

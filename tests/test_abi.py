@@ -117,10 +117,13 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_shadow_labels(P, N, 10, P, 32, None, 4, P, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_shadow_labels(P, N, 10, P, 128, P, 4097, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels(P, N, -1, P, 32, P, 16, P, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(P, P, P, P, 10, 0, N, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 1e-2, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_adam(None, P, P, P, 10, 1, N, 1e-2, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL
-    assert lib.nvc_adam(P, P, P, P, 10, 0, P, 1e-2, 0.9, 1.5, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 0, N, 1e-2, 1e-2, 0, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 1e-2, 1e-2, 0, 1.0, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(None, P, P, P, 10, 1, N, 1e-2, 1e-2, 0, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_adam(P, P, P, P, 10, 0, P, 1e-2, 1e-2, 0, 0.9, 1.5, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, 1e-3, -1, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, -1e-3, 200, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, float("nan"), 200, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_counters_advance(None, N) == _lib.NVC_ERR_NULL
 
 

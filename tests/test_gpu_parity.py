@@ -73,6 +73,7 @@ INFER_CASES = [
     ("tiny", "f32", 2e-5), ("tiny", "f16", 2e-3), ("tiny", "bf16", 3e-2),
     ("frame_1080p", "f32", 2e-5), ("frame_1080p", "f16", 2e-3), ("frame_1080p", "bf16", 3e-2),
     ("sweep_4k", "f32", 2e-5), ("sweep_4k", "f16", 2e-3), ("sweep_4k", "bf16", 3e-2),
+    ("paper_1080p", "f32", 2e-5), ("paper_1080p", "f16", 2e-3), ("paper_1080p", "bf16", 3e-2),
 ]
 
 
@@ -83,7 +84,8 @@ def test_infer_matches_oracle(wl_name, dtype, tol):
     cache = make_cache(wl, p, dtype=dtype)
     pos = rand_pos(13, 2085)                           # several tiles and a ragged tail
     vis = cache.infer(t(pos), dtype=torch.float32).cpu().numpy()
-    ref = pipeline.infer(pos, p["table"], p["weights"], wl.grid.base_res, wl.grid.growth)
+    ref = pipeline.infer(pos, p["table"], p["weights"], wl.grid.base_res, wl.grid.growth, act=wl.mlp.act,
+                         slope=wl.mlp.leaky_slope)
     err = np.abs(vis - ref)
     print(f"{wl_name} {dtype}: max|err| {err.max():.3e} mean {err.mean():.3e}")
     assert err.max() <= tol
@@ -125,7 +127,7 @@ def test_infer_outputs_in_every_dtype_agree():
 
 
 @pytest.mark.parametrize("wl_name,dtype", [(w, d) for w in ("tiny", "frame_1080p", "sweep_4k") for d in ("f32", "f16", "bf16")]
-                         + [("paper", "f16"), ("paper", "f32")])
+                         + [("paper", "f16"), ("paper", "bf16"), ("paper", "f32"), ("paper_1080p", "f16")])
 def test_mlp_forward_on_encoding_equals_fused_inference(wl_name, dtype):
     """nvc_mlp_forward(nvc_encode(x)) reproduces nvc_infer(x) bit for bit, with the encoding stored
     in the network's dtype and in FP32 (both round to the same matrix-core inputs)."""
@@ -246,6 +248,22 @@ def test_shadow_labels_bit_exact(small_scene, m):
     assert 0.05 < got.mean() < 0.999
 
 
+@pytest.mark.parametrize("batch,m", [(8192, 32), (1 << 18, 32), (1 << 17, 13)])
+def test_shadow_labels_large_batches_sampled(small_scene, batch, m):
+    """Batches large enough for eight lights per block (and the small-batch split of the lights over more
+    blocks at 8192): every label of a random subset of samples against the oracle."""
+    from paper_2506_05930_amd import api
+    sc = small_scene
+    rng = np.random.default_rng(100 + m)
+    lights = np.concatenate([rng.uniform(0.5, 9.5, (m, 3)), rng.uniform(0.5, 2, (m, 1))], 1).astype(np.float32)
+    pix = np.sort(philox.training_pixels(2, 3, batch, sc["pos"].shape[0]).astype(np.int32))
+    lab = torch.empty((batch, m), dtype=torch.uint8, device=DEV)
+    api.nvc_shadow_labels(t(sc["pos"]), t(pix), t(lights), t(sc["spheres"]), lab)
+    sub = rng.choice(batch, 2048, replace=False)
+    ref = shadow.labels_fp32(sc["pos"][pix[sub]], lights, sc["spheres"])
+    assert np.array_equal(lab.cpu().numpy()[sub], ref)
+
+
 def test_shadow_labels_unit_cube_without_indirection():
     from paper_2506_05930_amd import api
     sc = unit_cube_scene(0, 4096, 8, 16, n_train=1024)
@@ -264,7 +282,9 @@ def _rel_l2(a, b):
 
 GRAD_CASES = [("tiny", "f32", 1e-4, 1000), ("tiny", "f16", 3e-2, 1000), ("frame_1080p", "f32", 1e-4, 2085),
               ("frame_1080p", "f16", 3e-2, 2085), ("frame_1080p", "bf16", 1e-1, 2085),
-              ("sweep_4k", "f32", 1e-4, 700), ("sweep_4k", "f16", 3e-2, 700), ("sweep_4k", "bf16", 1e-1, 700)]
+              ("sweep_4k", "f32", 1e-4, 700), ("sweep_4k", "f16", 3e-2, 700), ("sweep_4k", "bf16", 1e-1, 700),
+              ("paper_1080p", "f32", 1e-4, 1500), ("paper_1080p", "f16", 3e-2, 1500),
+              ("paper_1080p", "bf16", 1e-1, 1500)]
 
 
 @pytest.mark.parametrize("wl_name,dtype,tol,batch", GRAD_CASES)
@@ -278,7 +298,7 @@ def test_train_gradients_match_oracle(wl_name, dtype, tol, batch, loss):
     y = (rng.uniform(size=(batch, wl.mlp.n_out)) > 0.4).astype(np.uint8)
     cache.gradients(t(pos), labels=t(y))
     ref = training.train_gradients(pos, p["table"], p["weights"], wl.grid.base_res, wl.grid.growth, labels=y,
-                                   loss=loss)
+                                   loss=loss, act=wl.mlp.act, slope=wl.mlp.leaky_slope)
     g_w = cache.g_w.cpu().numpy()
     ref_w = np.concatenate([g.ravel() for g in ref["g_w"]])
     g_t = cache.g_table.cpu().numpy()
@@ -340,6 +360,25 @@ def test_adam_matches_oracle():
     assert np.abs(M.cpu().numpy() - rm).max() <= 1e-7
     assert np.abs(V.cpu().numpy() - rv).max() <= 1e-9
     assert G.abs().max().item() == 0.0
+
+
+@pytest.mark.parametrize("step", [1, 2, 57, 200, 201, 350])
+def test_adam_learning_rate_schedule_matches_oracle(step):
+    """nvc_adam with the linear decay of Sec. 3.4 (0.05 -> 0.001 over 200 steps), step from the host and from
+    the device counter."""
+    from paper_2506_05930_amd import api
+    rng = np.random.default_rng(29)
+    n = 4099
+    p0, g0 = rng.normal(size=n).astype(np.float32), (rng.normal(size=n) * 1e-2).astype(np.float32)
+    m0, v0 = (rng.normal(size=n) * 1e-3).astype(np.float32), (rng.uniform(size=n) * 1e-4).astype(np.float32)
+    lr = training.learning_rate(step, 0.05, 0.001, 200)
+    rp, rm, rv = training.adam_step(p0, g0, m0, v0, step, lr, 0.9, 0.99, 1e-8)
+    for ctr in (None, api.new_counters(frame=0, step=step, device=DEV)):
+        P, G, M, V = t(p0), t(g0), t(m0), t(v0)
+        api.nvc_adam(P, G, M, V, step if ctr is None else 1, 0.05, 0.9, 0.99, 1e-8, ctr=ctr, lr_end=0.001,
+                     lr_decay_steps=200)
+        assert np.abs(P.cpu().numpy() - rp).max() <= 1e-6 * (1 + np.abs(rp).max())
+        assert np.abs(M.cpu().numpy() - rm).max() <= 1e-7
 
 
 def _straddling_points():

@@ -209,6 +209,34 @@ def test_adam_matches_torch_optim_adam_ten_steps():
         assert np.max(np.abs(pt.detach().numpy() - p)) <= 1e-12 * np.max(np.abs(p))
 
 
+def test_learning_rate_schedule_points():
+    """Sec. 3.4: start at 0.05, lowered linearly over the first 200 steps to 0.001, constant after."""
+    lr = [training.learning_rate(t, 0.05, 0.001, 200) for t in range(1, 400)]
+    assert lr[0] == 0.05 and lr[200] == 0.001 and lr[-1] == 0.001
+    assert abs(lr[100] - 0.0255) <= 1e-15                    # halfway: the mean of the two rates
+    steps = np.diff(lr[:201])
+    assert np.all(steps < 0) and np.allclose(steps, -0.049 / 200, rtol=1e-9, atol=0)
+    assert training.learning_rate(7, 0.01) == 0.01 and training.learning_rate(7, 0.01, 0.5, 0) == 0.01
+
+
+def test_adam_with_schedule_matches_torch_linear_lr():
+    """The schedule equals torch's LinearLR (factor 1 -> lr1/lr0 over D scheduler steps) driving torch Adam."""
+    rng = np.random.default_rng(6)
+    p0 = rng.normal(size=300)
+    pt = torch.from_numpy(p0.copy()).requires_grad_(True)
+    opt = torch.optim.Adam([pt], lr=0.05, betas=(0.9, 0.99), eps=1e-8)
+    sched = torch.optim.lr_scheduler.LinearLR(opt, start_factor=1.0, end_factor=0.001 / 0.05, total_iters=200)
+    p, m, v = p0.copy(), np.zeros(300), np.zeros(300)
+    for t in range(1, 231):
+        g = rng.normal(size=300) * 0.1
+        pt.grad = torch.from_numpy(g.copy())
+        assert abs(opt.param_groups[0]["lr"] - training.learning_rate(t, 0.05, 0.001, 200)) <= 1e-15
+        opt.step()
+        sched.step()
+        p, m, v = training.adam_step(p, g, m, v, t, training.learning_rate(t, 0.05, 0.001, 200), 0.9, 0.99, 1e-8)
+    assert np.max(np.abs(pt.detach().numpy() - p)) <= 1e-11 * np.max(np.abs(p))
+
+
 def test_adam_first_step_closed_form():
     # t = 1: m_hat = g, v_hat = g^2, so the step is lr * g / (|g| + eps).
     g = np.array([1.0, -2.0, 1e-3, 0.0])

@@ -84,6 +84,9 @@ class Workload:
     train_batch: int = 0
     loss: str = "bce"
     lr: float = 1e-2
+    lr_end: float | None = None  # with lr_decay_steps > 0: linear decay lr -> lr_end (Sec. 3.4)
+    lr_decay_steps: int = 0
+    init: str = "xavier"         # MLP initialisation: 'xavier' or 'he' (Sec. 3.4)
     beta1: float = 0.9
     beta2: float = 0.99
     adam_eps: float = 1e-8
@@ -129,6 +132,16 @@ WORKLOADS = {
         kind="boxes", width=3840, height=2160, n_boxes=64, n_lights=128, n_spheres=256,
         train_batch=1 << 18,
         notes="3840x2160, 128 lights, width-128 MLP; FP32 / FP16 / BF16 precision sweep",
+    ),
+    "paper_1080p": Workload(
+        name="paper_1080p",
+        grid=GridCfg(n_levels=10, n_feat=4, log2_T=14, base_res=16, growth=1.19),
+        mlp=MlpCfg(n_in=40, width=32, n_hidden=2, n_out=32, act="leaky", leaky_slope=0.01, dtype="f16"),
+        kind="boxes", width=1920, height=1080, n_boxes=64, n_lights=32, n_spheres=256,
+        train_batch=8192, loss="l2", lr=0.05, lr_end=0.001, lr_decay_steps=200, init="he",
+        notes="the paper's own configuration (Sec. 3.3-3.4): ten levels x four features at base 16 (T = 2^14, "
+              "growth 1.19), 40-32-32-32 MLP with leaky ReLU 0.01, L2 loss, He init, Adam with the rate lowered "
+              "linearly from 0.05 to 0.001 over the first 200 steps, 8192 screen samples per frame; 1080p box scene",
     ),
     "loop_60f": Workload(
         name="loop_60f", grid=_GRID_1080, mlp=_MLP_1080,
