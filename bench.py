@@ -399,6 +399,11 @@ def main():
     hbm = measured_traffic("infer", wl)
     roof["traffic"] = None if hbm is None else hbm / t_inf / 1e9
     roof["traffic_bytes_per_launch"] = hbm
+    if stage_ms is not None:
+        # the same kernel alone on the GPU (serial stage pass): inside the timed frames it shares the
+        # CUs with the training half on the other stream
+        roof["alone_ms"] = stage_ms["infer"]
+        roof["frac_alone"] = alg["infer"]["bytes"] / (stage_ms["infer"] / 1e3) / 1e9 / PEAK_HBM_GBS
 
     st = stage_ms if stage_ms is not None else timed_ms
     q_infer_wrs = n_pix / ((st["infer"] + st["wrs"]) / 1e3)

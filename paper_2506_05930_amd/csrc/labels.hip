@@ -140,17 +140,17 @@ __device__ inline uint32_t spread10(uint32_t v) {        // 10 bits -> every thi
 
 int cu_count();
 
-constexpr int kLabelBlock = 1024;   // samples per block (16 waves of 64)
+constexpr int kLabelBlock = 1024;   // samples per block (waves of 64; a power of two up to 1024)
 constexpr int kLabelLights = 8;     // most lights per block (grid.y covers all lights)
 
-// Block (x, y): samples [x*1024, x*1024 + 1024) and lights [lpb*y, lpb*y + lpb),
+// Block (x, y): samples [x*kLabelBlock, (x+1)*kLabelBlock) and lights [lpb*y, lpb*y + lpb),
 // lpb <= 8 lights per block (fewer when the batch is small, so that the grid
 // still covers the chip).  The
 // block sorts its samples by the 3D Morton code of their position inside the
 // block's bounding box, so each wave of 64 consecutive sorted samples is
 // compact in space (samples on both sides of a depth edge go to different
 // waves); labels are written at the samples' own rows.
-__global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ pos, const int32_t* __restrict__ pix,
+__global__ __launch_bounds__(kLabelBlock) void labels_kernel(const float* __restrict__ pos, const int32_t* __restrict__ pix,
                                                       int64_t n, const float* __restrict__ lights, int m,
                                                       const float* __restrict__ spheres, int n_spheres,
                                                       uint8_t* __restrict__ labels, int lpb) {
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ 
                 mn[k] = fminf(mn[k], __shfl_xor(mn[k], off));
                 mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
             }
-        __shared__ float wmn[16][3], wmx[16][3];
+        __shared__ float wmn[kLabelBlock / 64][3], wmx[kLabelBlock / 64][3];
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0)
             for (int k = 0; k < 3; ++k) { wmn[w][k] = mn[k]; wmx[w][k] = mx[k]; }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ 
         keys[threadIdx.x] = key | (uint64_t)threadIdx.x;
     }
     __syncthreads();
-    // Bitonic sort of the 1024 keys in LDS.
+    // Bitonic sort of the block's keys in LDS.
     for (int k = 2; k <= kLabelBlock; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
             const int i = threadIdx.x, ixj = i ^ jj;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(1024) void labels_kernel(const float* __restrict__ 
     }
 
     const int lane = threadIdx.x & 63;
-    const int local = (int)(keys[threadIdx.x] & 1023u);
+    const int local = (int)(keys[threadIdx.x] & (uint64_t)(kLabelBlock - 1));
     const int64_t b = (int64_t)blockIdx.x * kLabelBlock + local;
     const bool valid = b < n;
     const int64_t src = valid ? (pix ? (int64_t)pix[b] : b) : 0;
