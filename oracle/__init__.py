@@ -20,5 +20,6 @@ Modules (paper passages in brackets):
   shadow     shadow-ray labels against sphere occluders         [Sec. 3.4]
   training   loss, pixel selection, table gradient, Adam        [Sec. 3.3, Sec. 3.4]
   estimator  exact moments of the light-sampling estimator      [Sec. 1, Sec. 3.1]
+  clustered  k-means clusters, cluster labels, two-step sampling [Sec. 3.6]
   pipeline   the frame composed from the steps above
 """
