@@ -207,6 +207,64 @@ int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n,
                       const float* lights, int32_t m, const float* spheres, int32_t n_spheres,
                       uint8_t* labels, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Clustered cache (Sec. 3.6): the output neurons predict the average
+ * visibility of clusters of lights, so the light count is not bounded by the
+ * output layer.  A clustering is CSR: offsets int32 [k+1] (offsets[0] = 0,
+ * non-decreasing, offsets[k] = n_lights) and members int32 [n_lights], the
+ * light indices of cluster c in members[offsets[c] .. offsets[c+1]).  On the
+ * device, an ill-formed range or a member outside [0, n_lights) is treated as
+ * an empty cluster or a missing light, never read out of bounds.
+ * ------------------------------------------------------------------------- */
+
+/* Host only.  k-means clustering of the lights by position (Sec. 3.6).
+ * lights: HOST float32 [n_lights][4]; 1 <= k <= min(n_lights, 128); iters >= 1.
+ * Initial centroids by farthest points (light 0, then repeatedly the light
+ * farthest from the chosen ones, ties to the lower index); then Lloyd
+ * iterations in FP64: each light to its nearest centroid (squared distance
+ * (dx*dx + dy*dy) + dz*dz, ties to the lower cluster), each non-empty cluster's
+ * centroid to the mean of its lights (coordinates summed in light order),
+ * until no assignment changes or `iters` iterations ran.  Writes HOST offsets
+ * [k+1] and members [n_lights] (ascending light index within a cluster). */
+int nvc_cluster_lights(const float* lights, int32_t n_lights, int32_t k, int32_t iters, int32_t* offsets,
+                       int32_t* members);
+
+/* Clustered training labels (Sec. 3.6): for sample b (position pos[pix[b]],
+ * or pos[b] if pix is NULL) and cluster c, one light of the cluster is drawn
+ * uniformly, members[offsets[c] + ((r * m_c) >> 32)] with m_c the cluster's
+ * size and r word c%4 of Philox4x32-10 with counter (b lo32, b hi32, frame,
+ * 32 + c/4) and key (seed lo32, seed hi32), and labels[b][c] (uint8 [n][k])
+ * is 1 if the segment to it misses every sphere (the FP32 test of
+ * nvc_shadow_labels), else 0; 0 for an empty cluster.  Device pointers.
+ * 1 <= k <= 128, 0 <= n_spheres <= 4096; ctr as in nvc_sample_wrs. */
+int nvc_shadow_labels_clustered(const float* pos, const int32_t* pix, int64_t n, const float* lights,
+                                int32_t n_lights, const int32_t* offsets, const int32_t* members, int32_t k,
+                                const float* spheres, int32_t n_spheres, uint64_t seed, uint32_t frame,
+                                const nvc_counters* ctr, uint8_t* labels, void* stream);
+
+/* Two-step light pick of the clustered cache (Sec. 3.6), one per pixel.
+ * vis: [n][k] cluster visibilities in vis_dtype; pos, nrm, lights as in
+ * nvc_sample_wrs (lights [n_lights][4]).
+ * Step 1, WRS over the clusters: w_j = fl(m_j) * max(v_j, vis_floor) (m_j the
+ * cluster's size), the pick uniform and the inverse-CDF rule of
+ * nvc_sample_wrs give cluster y, P = w_y / W (W the sequential FP32 sum).
+ * Step 2, streaming RIS over n_cand candidates drawn uniformly from cluster
+ * y: candidate kk is members[offsets[y] + ((r * m_y) >> 32)], r word kk%4 of
+ * Philox with counter (pixel lo32, pixel hi32, frame, 4 + kk/4); its target
+ * is its unshadowed weight f (the order of nvc_sample_wrs) and its source
+ * pdf P / m_y.  With S the sequential FP32 sum of the candidates' f and u2
+ * from word 0 of counter (pixel, frame, 2), the kept candidate x is the first
+ * whose running sum exceeds u2 * S, and its contribution weight is
+ *   weight = (S * fl(m_y)) / ((fl(n_cand) * P) * f_x),
+ * so that f_x V_x weight is an unbiased estimate of sum_i f_i V_i.
+ * Outputs [n]: idx (int32, the light, -1 if W = 0 or S = 0), weight (float32,
+ * 0 then), cluster (int32 y or -1; may be NULL).  1 <= k <= 128,
+ * 1 <= n_cand <= 64; ctr as in nvc_sample_wrs. */
+int nvc_sample_clustered(const void* vis, int32_t vis_dtype, int64_t n, int32_t k, const float* pos,
+                         const float* nrm, const float* lights, int32_t n_lights, const int32_t* offsets,
+                         const int32_t* members, float vis_floor, int32_t n_cand, uint64_t seed, uint32_t frame,
+                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster, void* stream);
+
 /* Host only.  Workspace bytes nvc_train_step needs for this network and batch. */
 int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch);
 

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -188,6 +189,56 @@ def nvc_shadow_labels(pos: torch.Tensor, pix, lights: torch.Tensor, spheres: tor
     pb = _ptr(labels, "labels", torch.uint8)
     _lib.check("nvc_shadow_labels", _lib.load().nvc_shadow_labels(pp, px, n, pl, m, ps, spheres.shape[0], pb,
                                                                   _stream(stream)))
+
+
+def nvc_cluster_lights(lights, k: int, iters: int = 20):
+    """Host k-means of the lights (array-like [n][4] on the host) -> (offsets int32 [k+1], members int32 [n])."""
+    arr = np.ascontiguousarray(np.asarray(lights.cpu() if isinstance(lights, torch.Tensor) else lights,
+                                          dtype=np.float32))
+    if arr.ndim != 2 or arr.shape[1] != 4:
+        raise ValueError("lights must be [n][4]")
+    n = arr.shape[0]
+    offsets = np.zeros(k + 1, np.int32)
+    members = np.zeros(n, np.int32)
+    _lib.check("nvc_cluster_lights", _lib.load().nvc_cluster_lights(arr.ctypes.data, n, int(k), int(iters),
+                                                                    offsets.ctypes.data, members.ctypes.data))
+    return offsets, members
+
+
+def nvc_shadow_labels_clustered(pos: torch.Tensor, pix, lights: torch.Tensor, offsets: torch.Tensor,
+                                members: torch.Tensor, spheres: torch.Tensor, seed: int, frame: int,
+                                labels: torch.Tensor, stream=None, ctr=None) -> None:
+    n, k = labels.shape
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    px = _ptr(pix, "pix", torch.int32, (n,), optional=True)
+    if pix is None and pos.shape[0] < n:
+        raise ValueError("pos has fewer rows than labels")
+    pl = _ptr(lights, "lights", torch.float32, (None, 4))
+    po = _ptr(offsets, "offsets", torch.int32, (k + 1,))
+    pm = _ptr(members, "members", torch.int32, (lights.shape[0],))
+    ps = _ptr(spheres, "spheres", torch.float32, (None, 4)) if spheres.numel() else None
+    pb = _ptr(labels, "labels", torch.uint8)
+    _lib.check("nvc_shadow_labels_clustered", _lib.load().nvc_shadow_labels_clustered(
+        pp, px, n, pl, lights.shape[0], po, pm, k, ps, spheres.shape[0], int(seed) & (2 ** 64 - 1),
+        int(frame) & 0xFFFFFFFF, _counters(ctr), pb, _stream(stream)))
+
+
+def nvc_sample_clustered(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, offsets: torch.Tensor,
+                         members: torch.Tensor, vis_floor: float, n_cand: int, seed: int, frame: int,
+                         idx: torch.Tensor, weight: torch.Tensor, cluster=None, stream=None, ctr=None) -> None:
+    n, k = vis.shape
+    pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16))
+    pp = _ptr(pos, "pos", torch.float32, (n, 3))
+    pn = _ptr(nrm, "nrm", torch.float32, (n, 3), optional=True)
+    pl = _ptr(lights, "lights", torch.float32, (None, 4))
+    po = _ptr(offsets, "offsets", torch.int32, (k + 1,))
+    pm = _ptr(members, "members", torch.int32, (lights.shape[0],))
+    pi = _ptr(idx, "idx", torch.int32, (n,))
+    pw = _ptr(weight, "weight", torch.float32, (n,))
+    pc = _ptr(cluster, "cluster", torch.int32, (n,), optional=True)
+    _lib.check("nvc_sample_clustered", _lib.load().nvc_sample_clustered(
+        pv, _DT_CODE[vis.dtype], n, k, pp, pn, pl, lights.shape[0], po, pm, float(vis_floor), int(n_cand),
+        int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, _counters(ctr), pi, pw, pc, _stream(stream)))
 
 
 def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor, pix,

@@ -24,7 +24,8 @@ LIB_NAME = "libnvc.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["capi.cpp", "mlp.hip", "encode.hip", "sampling.hip", "train.hip", "route.hip", "labels.hip", "adam.hip"]
+SOURCES = ["capi.cpp", "mlp.hip", "encode.hip", "sampling.hip", "train.hip", "route.hip", "labels.hip", "adam.hip",
+           "clustered.hip"]
 ARCH = os.environ.get("NVC_OFFLOAD_ARCH", "gfx950")
 
 

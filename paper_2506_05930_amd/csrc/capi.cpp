@@ -202,6 +202,43 @@ int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n, const flo
     return hip_status(launch_labels(pos, pix, n, lights, m, spheres, n_spheres, labels, (hipStream_t)stream));
 }
 
+int nvc_cluster_lights(const float* lights, int32_t n_lights, int32_t k, int32_t iters, int32_t* offsets,
+                       int32_t* members) {
+    if (n_lights < 1 || k < 1 || k > 128 || k > n_lights || iters < 1) return NVC_ERR_SHAPE;
+    if (!lights || !offsets || !members) return NVC_ERR_NULL;
+    for (int64_t i = 0; i < 4 * (int64_t)n_lights; ++i)
+        if (!isfinite(lights[i])) return NVC_ERR_SHAPE;
+    cluster_lights_host(lights, n_lights, k, iters, offsets, members);
+    return NVC_OK;
+}
+
+int nvc_shadow_labels_clustered(const float* pos, const int32_t* pix, int64_t n, const float* lights,
+                                int32_t n_lights, const int32_t* offsets, const int32_t* members, int32_t k,
+                                const float* spheres, int32_t n_spheres, uint64_t seed, uint32_t frame,
+                                const nvc_counters* ctr, uint8_t* labels, void* stream) {
+    if (n < 0 || k < 1 || k > 128 || n_lights < 0 || n_spheres < 0 || n_spheres > 4096) return NVC_ERR_SHAPE;
+    if (n > ((int64_t)1 << 40) / k) return NVC_ERR_SHAPE;
+    if (n == 0) return NVC_OK;
+    if (!pos || !offsets || !labels || (n_lights > 0 && (!lights || !members)) || (n_spheres > 0 && !spheres))
+        return NVC_ERR_NULL;
+    return hip_status(launch_clustered_labels(pos, pix, n, lights, n_lights, offsets, members, k, spheres, n_spheres,
+                                              seed, frame, ctr ? &ctr->frame : nullptr, labels, (hipStream_t)stream));
+}
+
+int nvc_sample_clustered(const void* vis, int32_t vis_dtype, int64_t n, int32_t k, const float* pos,
+                         const float* nrm, const float* lights, int32_t n_lights, const int32_t* offsets,
+                         const int32_t* members, float vis_floor, int32_t n_cand, uint64_t seed, uint32_t frame,
+                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster, void* stream) {
+    if (n < 0 || k < 1 || k > 128 || n_lights < 0 || n_cand < 1 || n_cand > 64) return NVC_ERR_SHAPE;
+    if (vis_dtype != NVC_F32 && vis_dtype != NVC_F16 && vis_dtype != NVC_BF16) return NVC_ERR_DTYPE;
+    if (!(vis_floor >= 0.0f) || !isfinite(vis_floor)) return NVC_ERR_SHAPE;
+    if (n == 0) return NVC_OK;
+    if (!vis || !pos || !offsets || !idx || !weight || (n_lights > 0 && (!lights || !members))) return NVC_ERR_NULL;
+    return hip_status(launch_clustered_sample(vis, vis_dtype, n, k, pos, nrm, lights, n_lights, offsets, members,
+                                              vis_floor, n_cand, seed, frame, ctr ? &ctr->frame : nullptr, idx,
+                                              weight, cluster, (hipStream_t)stream));
+}
+
 int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch) {
     GridHost g{};
     NetShape s{};

@@ -128,6 +128,29 @@ __device__ inline uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t 
     return c0;
 }
 
+// All four output words of the same generator.
+__device__ inline void philox_words(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1,
+                                    uint32_t (&out)[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
 // --------------------------------------------------------------- hash grid
 struct GridDev {
     int32_t n_levels;
@@ -408,6 +431,21 @@ __device__ inline float sigmoidf_(float z) { return sigmoid_from(z, exp_neg_abs(
 // 0; relative error a few 1e-7 (as sigmoidf_ for |z| < 16).
 __device__ inline float sigmoid_fast(float z) {
     return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.44269504088896341f));
+}
+
+// --------------------------------------------------------------- lights
+// Unshadowed weight f and light weight w = f * max(v, floor) of light l at p (order as in nvc.h).
+__device__ inline void wrs_weight(const float4& l, float px, float py, float pz, float nx, float ny, float nz,
+                                  bool has_n, float v, float vis_floor, float& f, float& w) {
+    const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
+    const float d2 = fmaxf((dx * dx + dy * dy) + dz * dz, 1e-6f);
+    if (has_n) {
+        const float nd = (nx * dx + ny * dy) + nz * dz;
+        f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
+    } else {
+        f = __fdiv_rn(l.w, d2);
+    }
+    w = f * fmaxf(v, vis_floor);
 }
 
 }  // namespace nvc

@@ -92,6 +92,16 @@ hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& pl
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
                        float lr, float lr_end, int lr_decay_steps, float beta1, float beta2, float eps, int zero_grad,
                        hipStream_t st);
+hipError_t launch_clustered_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int n_lights,
+                                   const int32_t* offsets, const int32_t* members, int k, const float* spheres,
+                                   int n_spheres, uint64_t seed, uint32_t frame, const uint32_t* frame_dev,
+                                   uint8_t* labels, hipStream_t st);
+hipError_t launch_clustered_sample(const void* vis, int vis_dtype, int64_t n, int k, const float* pos, const float* nrm,
+                                   const float* lights, int n_lights, const int32_t* offsets, const int32_t* members,
+                                   float vis_floor, int n_cand, uint64_t seed, uint32_t frame,
+                                   const uint32_t* frame_dev, int32_t* idx, float* weight, int32_t* cluster,
+                                   hipStream_t st);
+void cluster_lights_host(const float* lights, int n, int k, int iters, int32_t* offsets, int32_t* members);
 // frame += 1, step += 1 of the device counters {uint32 frame; int32 step}.
 hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st);
 

@@ -23,20 +23,6 @@ namespace nvc {
 // which reproduces C_i exactly.
 constexpr int kWrsThreads = 256;
 
-// Unshadowed weight f and light weight w = f * max(v, floor) of light l at p (order as in nvc.h).
-__device__ inline void wrs_weight(const float4& l, float px, float py, float pz, float nx, float ny, float nz,
-                                  bool has_n, float v, float vis_floor, float& f, float& w) {
-    const float dx = l.x - px, dy = l.y - py, dz = l.z - pz;
-    const float d2 = fmaxf((dx * dx + dy * dy) + dz * dz, 1e-6f);
-    if (has_n) {
-        const float nd = (nx * dx + ny * dy) + nz * dz;
-        f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
-    } else {
-        f = __fdiv_rn(l.w, d2);
-    }
-    w = f * fmaxf(v, vis_floor);
-}
-
 // The eight visibilities of group g of a row (missing lights read as 0).
 template <typename VT>
 __device__ inline void wrs_load8(const VT* __restrict__ row, int g, int m, bool vec, float (&v)[8]) {

@@ -125,6 +125,37 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, -1e-3, 200, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, float("nan"), 200, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_counters_advance(None, N) == _lib.NVC_ERR_NULL
+    # clustered cache
+    assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, P, P, 0, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, P, P, 129, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, None, P, 32, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_shadow_labels_clustered(P, N, 0, P, 100, P, P, 32, P, 16, 0, 0, N, P, N) == 0
+    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 0, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 65, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, -1.0, 8, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_clustered(P, 7, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, None, P, N, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_cluster_lights(P, 10, 11, 5, P, P) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_cluster_lights(P, 10, 0, 5, P, P) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_cluster_lights(None, 10, 4, 5, P, P) == _lib.NVC_ERR_NULL
+
+
+def test_host_kmeans_equals_the_oracle():
+    """nvc_cluster_lights (host C++) and the oracle's k-means reach the same partition."""
+    import numpy as np
+
+    from oracle import clustered
+    from paper_2506_05930_amd import api
+    from workloads import box_scene
+    for seed, n, k in ((0, 300, 32), (1, 4096, 32), (2, 64, 64), (3, 1000, 7)):
+        lights = box_scene(seed, 8, 8, 4, n, 4)["lights"]
+        off, mem = api.nvc_cluster_lights(lights, k, 20)
+        ro, rm = clustered.kmeans(lights, k, 20)
+        assert np.array_equal(off, ro) and np.array_equal(mem, rm), (seed, n, k)
+    bad = np.ones((5, 4), np.float32)
+    bad[2, 1] = np.nan
+    with pytest.raises(Exception):
+        api.nvc_cluster_lights(bad, 2, 5)
 
 
 def test_train_step_validation(lib):

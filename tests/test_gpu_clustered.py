@@ -1,0 +1,125 @@
+"""Clustered cache kernels against the oracle (Sec. 3.6).
+
+Cluster partitions here are seeded random inputs (not k-means), with an empty
+cluster and a one-light cluster among them, so that the label and sampling
+kernels are checked on any partition; the library's k-means is checked
+against the oracle's in the ABI tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import clustered, lighting, philox
+from workloads import box_scene
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def t(x):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return box_scene(0, 160, 90, 64, 300, 256)
+
+
+def random_partition(seed, n_lights, k):
+    """CSR partition of the lights into k clusters: cluster 1 empty, cluster 2 one light."""
+    rng = np.random.default_rng(seed)
+    lab = rng.integers(0, k, n_lights)
+    lab[lab == 1] = 0
+    lab[lab == 2] = 3
+    lab[rng.integers(0, n_lights)] = 2
+    members = np.argsort(lab, kind="stable")
+    offsets = np.concatenate([[0], np.cumsum(np.bincount(lab, minlength=k))])
+    return offsets.astype(np.int32), members.astype(np.int32)
+
+
+@pytest.mark.parametrize("k", [32, 13])
+def test_clustered_labels_bit_exact(scene, k):
+    from paper_2506_05930_amd import api
+    off, mem = random_partition(k, scene["lights"].shape[0], k)
+    n = 3001
+    pix = np.sort(philox.training_pixels(2, 5, n, scene["pos"].shape[0])).astype(np.int32)
+    lab = torch.empty((n, k), dtype=torch.uint8, device=DEV)
+    api.nvc_shadow_labels_clustered(t(scene["pos"]), t(pix), t(scene["lights"]), t(off), t(mem), t(scene["spheres"]),
+                                    2, 5, lab)
+    choice = clustered.training_lights(2, 5, n, off, mem)
+    ref = clustered.labels(scene["pos"][pix], scene["lights"], scene["spheres"], choice)
+    got = lab.cpu().numpy()
+    assert np.array_equal(got, ref)
+    assert np.all(got[:, 1] == 0) and 0.05 < got.mean() < 0.99
+
+
+def test_clustered_labels_device_frame_counter(scene):
+    from paper_2506_05930_amd import api
+    off, mem = random_partition(3, scene["lights"].shape[0], 32)
+    n = 777
+    a = torch.empty((n, 32), dtype=torch.uint8, device=DEV)
+    b = torch.empty_like(a)
+    api.nvc_shadow_labels_clustered(t(scene["pos"]), None, t(scene["lights"]), t(off), t(mem), t(scene["spheres"]),
+                                    2, 9, a)
+    api.nvc_shadow_labels_clustered(t(scene["pos"]), None, t(scene["lights"]), t(off), t(mem), t(scene["spheres"]),
+                                    2, 0, b, ctr=api.new_counters(frame=9, device=DEV))
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("vdt,n_cand,with_n", [(torch.float32, 8, True), (torch.float16, 3, True),
+                                               (torch.bfloat16, 8, False), (torch.float16, 1, True),
+                                               (torch.float32, 64, True)])
+def test_clustered_sample_bit_exact(scene, vdt, n_cand, with_n):
+    from paper_2506_05930_amd import api
+    k = 32
+    off, mem = random_partition(7, scene["lights"].shape[0], k)
+    n = 4099
+    rng = np.random.default_rng(11)
+    sel = rng.choice(scene["pos"].shape[0], n, replace=False)
+    pos, nrm = scene["pos"][sel], scene["nrm"][sel] if with_n else None
+    vis = t(rng.uniform(0, 1, (n, k)).astype(np.float32)).to(vdt)
+    vis[:7] = 0                                                       # floor-only rows
+    idx = torch.empty(n, dtype=torch.int32, device=DEV)
+    w = torch.empty(n, dtype=torch.float32, device=DEV)
+    cl = torch.empty(n, dtype=torch.int32, device=DEV)
+    api.nvc_sample_clustered(vis, t(pos), None if nrm is None else t(nrm), t(scene["lights"]), t(off), t(mem),
+                             1e-3, n_cand, 2, 4, idx, w, cl)
+    ref = clustered.sample(vis.float().cpu().numpy(), pos, nrm, scene["lights"], off, mem, 2, 4, n_cand,
+                           dtype=np.float32)
+    assert np.array_equal(cl.cpu().numpy(), ref["cluster"])
+    assert np.array_equal(idx.cpu().numpy(), ref["idx"])
+    assert np.array_equal(w.cpu().numpy(), ref["W"])
+    assert np.all(cl.cpu().numpy() != 1)                             # the empty cluster is never picked
+
+
+def test_clustered_sample_is_unbiased_on_the_gpu(scene):
+    """f_x V_x W over 2^20 independent picks at one point against the exact sum_i f_i V_i."""
+    from paper_2506_05930_amd import api
+    k = 32
+    off, mem = random_partition(8, scene["lights"].shape[0], k)
+    n = 1 << 20
+    from oracle import shadow
+    # the point (of 64 candidates) with the most lights both visible and facing it
+    cand = np.random.default_rng(3).choice(scene["pos"].shape[0], 64, replace=False)
+    fc = lighting.unshadowed_weight(scene["pos"][cand], scene["nrm"][cand], scene["lights"])
+    Vc = shadow.labels(scene["pos"][cand], scene["lights"], scene["spheres"])
+    best = cand[np.argmax(((fc > 0) & (Vc > 0)).sum(1))]
+    p0, n0 = scene["pos"][best], scene["nrm"][best]
+    pos = np.tile(p0, (n, 1)).astype(np.float32)
+    nrm = np.tile(n0, (n, 1)).astype(np.float32)
+    V = shadow.labels(p0[None, :], scene["lights"], scene["spheres"])[0].astype(np.float64)
+    # cluster visibilities: a rough guess (the mean of V over the cluster, floored) -- any positive values do
+    vc = np.array([V[mem[off[j]:off[j + 1]]].mean() if off[j + 1] > off[j] else 0.0 for j in range(k)], np.float32)
+    vis = t(np.tile(vc, (n, 1)))
+    idx = torch.empty(n, dtype=torch.int32, device=DEV)
+    w = torch.empty(n, dtype=torch.float32, device=DEV)
+    api.nvc_sample_clustered(vis, t(pos), t(nrm), t(scene["lights"]), t(off), t(mem), 1e-3, 8, 2, 7, idx, w)
+    f = lighting.unshadowed_weight(p0[None, :], n0[None, :], scene["lights"])[0]
+    ii = idx.cpu().numpy()
+    est = np.where(ii >= 0, f[np.maximum(ii, 0)] * V[np.maximum(ii, 0)] * w.cpu().numpy().astype(np.float64), 0.0)
+    mu = (f * V).sum()
+    se = est.std() / np.sqrt(n)
+    print(f"mean {est.mean():.6g} exact {mu:.6g} se {se:.3g}")
+    assert mu > 0 and ((f > 0) & (V > 0)).sum() >= 20
+    assert abs(est.mean() - mu) <= 4.5 * se
