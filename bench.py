@@ -88,19 +88,30 @@ def cpu_baseline(wl, scene, params, sample_pix: int):
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    from oracle import hashgrid, lighting, philox, pipeline, shadow, training
+    from oracle import clustered, hashgrid, lighting, philox, pipeline, shadow, training
 
     n_pix = scene["pos"].shape[0]
     sel = np.arange(sample_pix)
     batch_s = max(1024, wl.train_batch // 2)
+    if wl.n_clusters:
+        off, mem = clustered.kmeans(scene["lights"], wl.n_clusters)
+        batch_s = min(batch_s, 8192)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         vis = pipeline.infer(scene["pos_unit"][sel], params["table"], params["weights"], wl.grid.base_res,
                              wl.grid.growth, act=wl.mlp.act, slope=wl.mlp.leaky_slope)
-        pipeline.sample(vis, scene["pos"][sel], scene["nrm"][sel], scene["lights"], wl.rng_key, 0, wl.vis_floor)
+        if wl.n_clusters:
+            clustered.sample(vis, scene["pos"][sel], scene["nrm"][sel], scene["lights"], off, mem, wl.rng_key, 0,
+                             wl.n_cand, wl.vis_floor, dtype=np.float64)
+        else:
+            pipeline.sample(vis, scene["pos"][sel], scene["nrm"][sel], scene["lights"], wl.rng_key, 0, wl.vis_floor)
         t1 = time.perf_counter()
         pix = philox.training_pixels(wl.rng_key, 0, batch_s, n_pix)
-        y = shadow.labels_fp32(scene["pos"][pix], scene["lights"], scene["spheres"])
+        if wl.n_clusters:
+            y = clustered.labels(scene["pos"][pix], scene["lights"], scene["spheres"],
+                                 clustered.training_lights(wl.rng_key, 0, batch_s, off, mem))
+        else:
+            y = shadow.labels_fp32(scene["pos"][pix], scene["lights"], scene["spheres"])
         g = training.train_gradients(scene["pos_unit"][pix], params["table"], params["weights"], wl.grid.base_res,
                                      wl.grid.growth, labels=y, loss=wl.loss, act=wl.mlp.act, slope=wl.mlp.leaky_slope)
         t2 = time.perf_counter()
@@ -292,8 +303,14 @@ def main():
     lights = torch.as_tensor(scene["lights"]).to(dev)
     spheres = torch.as_tensor(scene["spheres"]).to(dev)
     vis = torch.empty((n_pix, wl.mlp.n_out), dtype=cache.vis_dtype, device=dev)
-    out = {k: torch.empty(n_pix, dtype=d, device=dev) for k, d in
-           (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
+    clustered = wl.n_clusters > 0
+    if clustered:                      # Sec. 3.6: one output per k-means cluster of the lights
+        cache.set_clusters(*api.nvc_cluster_lights(scene["lights"], wl.n_clusters), n_cand=wl.n_cand)
+        out = {k: torch.empty(n_pix, dtype=d, device=dev) for k, d in
+               (("idx", torch.int32), ("weight", torch.float32), ("cluster", torch.int32))}
+    else:
+        out = {k: torch.empty(n_pix, dtype=d, device=dev) for k, d in
+               (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
     pix = torch.empty(B, dtype=torch.int32, device=dev)
     labels = torch.empty((B, wl.mlp.n_out), dtype=torch.uint8, device=dev)
     pix_ws = cache.pixel_workspace(n_pix)
@@ -307,6 +324,21 @@ def main():
 
     side = torch.cuda.Stream()
 
+    def do_sample(frame, st=None):
+        if clustered:
+            api.nvc_sample_clustered(vis, pos, nrm, lights, cache.cl_offsets, cache.cl_members, cache.vis_floor,
+                                     cache.n_cand, cache.seed, frame, out["idx"], out["weight"], out["cluster"], st)
+        else:
+            api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
+                               out["wsum"], out["di"], st)
+
+    def do_labels(frame, st=None):
+        if clustered:
+            api.nvc_shadow_labels_clustered(pos, pix, lights, cache.cl_offsets, cache.cl_members, spheres, cache.seed,
+                                            frame, labels, st)
+        else:
+            api.nvc_shadow_labels(pos, pix, lights, spheres, labels, st)
+
     def step(frame, ev=None, kev=None):
         """One frame.  Timed frames run the training half (pixels, labels, gradients) on a second
         stream beside inference + WRS, joining before Adam (`kev`: events around the inference and
@@ -315,15 +347,14 @@ def main():
         if ev is None:
             side.wait_stream(stream)
             api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws, side)
-            api.nvc_shadow_labels(pos, pix, lights, spheres, labels, side)
+            do_labels(frame, side)
             cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=side)
             if kev is not None:
                 kev[0].record(stream)
             api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis, stream)
             if kev is not None:
                 kev[1].record(stream)
-            api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
-                               out["wsum"], out["di"], stream)
+            do_sample(frame, stream)
             if kev is not None:
                 kev[2].record(stream)
             stream.wait_stream(side)
@@ -332,12 +363,11 @@ def main():
         ev[0].record(stream)
         api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis)
         ev[1].record(stream)
-        api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
-                           out["wsum"], out["di"])
+        do_sample(frame)
         ev[2].record(stream)
         api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws)
         ev[3].record(stream)
-        api.nvc_shadow_labels(pos, pix, lights, spheres, labels)
+        do_labels(frame)
         ev[4].record(stream)
         cache.gradients(pos_unit, labels=labels, pix=pix, batch=B)
         ev[5].record(stream)

@@ -76,6 +76,20 @@ class NVCache:
     def pack(self, stream=None):
         api.nvc_pack_mlp(self.mlp, self.w, self.packed, stream)
 
+    def set_clusters(self, offsets, members, n_cand: int = 8):
+        """Clustered cache (Sec. 3.6): output j is the visibility of cluster j of the lights (CSR offsets
+        [k+1], members [n_lights], e.g. from api.nvc_cluster_lights).  sample() then takes the two-step pick
+        with n_cand RIS candidates and the training labels shoot one ray per cluster."""
+        if len(offsets) != self.mlp.n_out + 1:
+            raise ValueError("one cluster per network output expected")
+        self.cl_offsets = torch.as_tensor(np.asarray(offsets, np.int32)).to(self.device)
+        self.cl_members = torch.as_tensor(np.asarray(members, np.int32)).to(self.device)
+        self.n_cand = int(n_cand)
+
+    @property
+    def clustered(self) -> bool:
+        return getattr(self, "cl_offsets", None) is not None
+
     # ------------------------------------------------------------ inference and sampling
     def infer(self, pos_unit: torch.Tensor, vis: torch.Tensor | None = None, dtype=None, stream=None) -> torch.Tensor:
         if vis is None:
@@ -92,6 +106,15 @@ class NVCache:
     def sample(self, vis, pos, nrm, lights, frame: int, out: dict | None = None, with_di: bool = True,
                stream=None, ctr=None) -> dict:
         n = vis.shape[0]
+        if self.clustered:
+            if out is None:
+                out = {"idx": torch.empty(n, dtype=torch.int32, device=self.device),
+                       "weight": torch.empty(n, dtype=torch.float32, device=self.device),
+                       "cluster": torch.empty(n, dtype=torch.int32, device=self.device)}
+            api.nvc_sample_clustered(vis, pos, nrm, lights, self.cl_offsets, self.cl_members, self.vis_floor,
+                                     self.n_cand, self.seed, frame, out["idx"], out["weight"], out["cluster"], stream,
+                                     ctr=ctr)
+            return out
         if out is None:
             out = {"idx": torch.empty(n, dtype=torch.int32, device=self.device),
                    "pmf": torch.empty(n, dtype=torch.float32, device=self.device),
@@ -132,7 +155,11 @@ class NVCache:
                     "labels": torch.empty((batch, self.mlp.n_out), dtype=torch.uint8, device=self.device)}
         api.nvc_select_pixels(self.seed, frame, pos_unit.shape[0], bufs["pix"], self.pixel_workspace(pos_unit.shape[0]),
                               stream, ctr=ctr)
-        api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
+        if self.clustered:
+            api.nvc_shadow_labels_clustered(pos_scene, bufs["pix"], lights, self.cl_offsets, self.cl_members, spheres,
+                                            self.seed, frame, bufs["labels"], stream, ctr=ctr)
+        else:
+            api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
         self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
         return bufs
 

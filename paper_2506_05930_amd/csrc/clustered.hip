@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kClLabelThreads) void clustered_labels_kernel(
                 const bool near_p = bb <= 0.0f;
                 const bool near_l = !near_p && bb >= dd;
                 const bool o = near_p ? cc < 0.0f : (near_l ? ((ex * ex + ey * ey) + ez * ez) < q.w : cc * dd < bb * bb);
-                occ = occ || o;
+                occ = occ || o;                    // no early exit: lanes stay converged
             }
             vis = occ ? 0 : 1;
         }
@@ -108,7 +108,10 @@ __device__ inline void ris_candidate(const uint32_t (&w)[4], int kk, const int32
     wrs_weight(L, px, py, pz, nx, ny, nz, has_n, 1.0f, 0.0f, f, wdummy);
 }
 
-template <typename VT>
+// NC > 0: the candidate count is NC (compile time) and the candidates stay in
+// registers between the two passes; NC = 0: n_cand at run time, pass 2
+// recomputes them.
+template <typename VT, int NC>
 __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
     const VT* __restrict__ vis, int64_t n, int k, const float* __restrict__ pos, const float* __restrict__ nrm,
     const float* __restrict__ lights, int n_lights, const int32_t* __restrict__ offsets,
@@ -175,15 +178,24 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
             nz = nrm[p * 3 + 2];
         }
         // Step 2: streaming RIS over n_cand uniform candidates of cluster y, target f.
-        // Pass 1: S = sum of f (sequential).  Pass 2: the same candidates again, up to the pick.
+        // Pass 1: S = sum of f (sequential).  Pass 2: the running sum again, up to the pick.
+        if constexpr (NC > 0) n_cand = NC;
+        constexpr int NR = NC > 0 ? NC : 1;
+        int cl_l[NR];
+        float cl_f[NR];
         float Ssum = 0.0f, flast = 0.0f;
         int llast = -1;
         uint32_t w4[4];
-        for (int kk = 0; kk < n_cand; ++kk) {
+#pragma unroll
+        for (int kk = 0; kk < (NC > 0 ? NC : n_cand); ++kk) {
             if (kk % 4 == 0) philox_words(plo, phi, fr, kTagRisCand + (uint32_t)(kk / 4), k0, k1, w4);
             int l;
             float f;
             ris_candidate(w4, kk, members, o0, m, n_lights, lights, px, py, pz, nx, ny, nz, has_n, l, f);
+            if constexpr (NC > 0) {
+                cl_l[kk] = l;
+                cl_f[kk] = f;
+            }
             Ssum = Ssum + f;
             if (f > 0.0f) {
                 llast = l;
@@ -194,15 +206,26 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
             const uint32_t r2 = philox_first_word(plo, phi, fr, kTagRisSelect, k0, k1);
             const float t2 = ((float)(r2 >> 8) * 0x1.0p-24f) * Ssum;
             float C = 0.0f, fx = 0.0f;
-            for (int kk = 0; kk < n_cand && pick < 0; ++kk) {
-                if (kk % 4 == 0) philox_words(plo, phi, fr, kTagRisCand + (uint32_t)(kk / 4), k0, k1, w4);
-                int l;
-                float f;
-                ris_candidate(w4, kk, members, o0, m, n_lights, lights, px, py, pz, nx, ny, nz, has_n, l, f);
-                C = C + f;
-                if (C > t2) {
-                    pick = l;
-                    fx = f;
+            if constexpr (NC > 0) {
+#pragma unroll
+                for (int kk = 0; kk < NC; ++kk) {
+                    C = C + cl_f[kk];
+                    if (pick < 0 && C > t2) {
+                        pick = cl_l[kk];
+                        fx = cl_f[kk];
+                    }
+                }
+            } else {
+                for (int kk = 0; kk < n_cand && pick < 0; ++kk) {
+                    if (kk % 4 == 0) philox_words(plo, phi, fr, kTagRisCand + (uint32_t)(kk / 4), k0, k1, w4);
+                    int l;
+                    float f;
+                    ris_candidate(w4, kk, members, o0, m, n_lights, lights, px, py, pz, nx, ny, nz, has_n, l, f);
+                    C = C + f;
+                    if (C > t2) {
+                        pick = l;
+                        fx = f;
+                    }
                 }
             }
             if (pick < 0) {                        // only through rounding
@@ -219,6 +242,10 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
 }
 
 // ------------------------------------------------------------------ host
+// The visibility pointer type of a clustered_sample_kernel instance (its first parameter).
+template <typename VT, typename... R>
+const VT* kern_vis_type(void (*)(const VT*, R...));
+
 hipError_t launch_clustered_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int n_lights,
                                    const int32_t* offsets, const int32_t* members, int k, const float* spheres,
                                    int n_spheres, uint64_t seed, uint32_t frame, const uint32_t* frame_dev,
@@ -239,18 +266,18 @@ hipError_t launch_clustered_sample(const void* vis, int vis_dtype, int64_t n, in
                                    hipStream_t st) {
     const unsigned blocks = (unsigned)((n + kClSampleThreads - 1) / kClSampleThreads);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    auto go = [&](auto kern, const void* v) {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(kClSampleThreads), 0, st,
+                           reinterpret_cast<decltype(kern_vis_type(kern))>(v), n, k, pos, nrm, lights, n_lights, offsets,
+                           members, vis_floor, n_cand, k0, k1, frame, frame_dev, idx, weight, cluster);
+    };
+    const bool c8 = n_cand == 8;
     if (vis_dtype == DT_F32)
-        hipLaunchKernelGGL(clustered_sample_kernel<float>, dim3(blocks), dim3(kClSampleThreads), 0, st,
-                           (const float*)vis, n, k, pos, nrm, lights, n_lights, offsets, members, vis_floor, n_cand,
-                           k0, k1, frame, frame_dev, idx, weight, cluster);
+        c8 ? go(clustered_sample_kernel<float, 8>, vis) : go(clustered_sample_kernel<float, 0>, vis);
     else if (vis_dtype == DT_F16)
-        hipLaunchKernelGGL(clustered_sample_kernel<_Float16>, dim3(blocks), dim3(kClSampleThreads), 0, st,
-                           (const _Float16*)vis, n, k, pos, nrm, lights, n_lights, offsets, members, vis_floor, n_cand,
-                           k0, k1, frame, frame_dev, idx, weight, cluster);
+        c8 ? go(clustered_sample_kernel<_Float16, 8>, vis) : go(clustered_sample_kernel<_Float16, 0>, vis);
     else
-        hipLaunchKernelGGL(clustered_sample_kernel<__bf16>, dim3(blocks), dim3(kClSampleThreads), 0, st,
-                           (const __bf16*)vis, n, k, pos, nrm, lights, n_lights, offsets, members, vis_floor, n_cand,
-                           k0, k1, frame, frame_dev, idx, weight, cluster);
+        c8 ? go(clustered_sample_kernel<__bf16, 8>, vis) : go(clustered_sample_kernel<__bf16, 0>, vis);
     return hipGetLastError();
 }
 

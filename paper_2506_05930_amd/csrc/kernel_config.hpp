@@ -34,6 +34,10 @@ template <class Fn> inline void for_each_config(Fn&& f) {
     f(Tag<Cfg<DT_F16, 2, 8, 8, 3, 2, 2>>{});
     f(Tag<Cfg<DT_BF16, 2, 8, 8, 3, 2, 2>>{});
     f(Tag<Cfg<DT_F32, 2, 8, 8, 3, 2, 1>>{});
+    // 32 -> 32 -> 32 -> 32 (clustered cache: eight levels of four features, 32 clusters, Sec. 3.6)
+    f(Tag<Cfg<DT_F16, 2, 2, 2, 2, 4, 2>>{});
+    f(Tag<Cfg<DT_BF16, 2, 2, 2, 2, 4, 2>>{});
+    f(Tag<Cfg<DT_F32, 2, 2, 2, 2, 4, 2>>{});
     // 40 -> 32 -> 32 -> 32 (the paper's network: ten levels of four features, Sec. 3.3)
     f(Tag<Cfg<DT_F16, 4, 2, 2, 2, 4, 2>>{});
     f(Tag<Cfg<DT_BF16, 4, 2, 2, 2, 4, 2>>{});

@@ -87,6 +87,8 @@ class Workload:
     lr_end: float | None = None  # with lr_decay_steps > 0: linear decay lr -> lr_end (Sec. 3.4)
     lr_decay_steps: int = 0
     init: str = "xavier"         # MLP initialisation: 'xavier' or 'he' (Sec. 3.4)
+    n_clusters: int = 0          # clustered cache (Sec. 3.6): one output per cluster of lights (0: per light)
+    n_cand: int = 8              # RIS candidates of the clustered pick
     beta1: float = 0.9
     beta2: float = 0.99
     adam_eps: float = 1e-8
@@ -142,6 +144,17 @@ WORKLOADS = {
         notes="the paper's own configuration (Sec. 3.3-3.4): ten levels x four features at base 16 (T = 2^14, "
               "growth 1.19), 40-32-32-32 MLP with leaky ReLU 0.01, L2 loss, He init, Adam with the rate lowered "
               "linearly from 0.05 to 0.001 over the first 200 steps, 8192 screen samples per frame; 1080p box scene",
+    ),
+    "clustered_1080p": Workload(
+        name="clustered_1080p",
+        grid=GridCfg(n_levels=8, n_feat=4, log2_T=14, base_res=2, growth=2.0),
+        mlp=MlpCfg(n_in=32, width=32, n_hidden=2, n_out=32, act="leaky", leaky_slope=0.01, dtype="f16"),
+        kind="boxes", width=1920, height=1080, n_boxes=64, n_lights=4096, n_spheres=256,
+        train_batch=49152, loss="l2", lr=0.05, lr_end=0.001, lr_decay_steps=200, init="he",
+        n_clusters=32, n_cand=8,
+        notes="clustered cache (Sec. 3.6): 4096 point lights in 32 k-means clusters, one output per cluster, "
+              "eight levels x four features at base 2 (growth 2.0, T = 2^14), 32-32-32-32 leaky MLP, L2, "
+              "49,152 samples per frame, two-step pick with 8 RIS candidates; 1080p box scene",
     ),
     "loop_60f": Workload(
         name="loop_60f", grid=_GRID_1080, mlp=_MLP_1080,
