@@ -27,6 +27,7 @@ MASK32 = 0xFFFFFFFF
 
 TAG_WRS = 0
 TAG_TRAIN_PIXEL = 1
+TAG_WORLD_POINT = 6
 
 
 def philox4x32_10(ctr, key):
@@ -65,6 +66,20 @@ def wrs_uniforms(seed: int, frame: int, n: int, first: int = 0) -> np.ndarray:
     """The light-selection uniform of pixels first..first+n-1 (tag 0)."""
     r = philox4x32_10(_counter(np.arange(first, first + n, dtype=np.uint64), frame, TAG_WRS), _key(seed))
     return uniform24(r[0])
+
+
+def world_points(seed: int, frame: int, n: int, box, extent: float):
+    """World-space training points (Sec. 3.4: samples at random scene positions, not only on the visible
+    surfaces): point i is lo + u * (hi - lo) per axis with u = uniform24 of words 0, 1, 2 of counter
+    (i, frame, 6), in FP32 (ext = hi - lo, then u * ext, then + lo); its unit-cube position is p / extent
+    (FP32 division).  Returns (pos_scene [n,3], pos_unit [n,3]) float32."""
+    r = philox4x32_10(_counter(np.arange(n, dtype=np.uint64), frame, TAG_WORLD_POINT), _key(seed))
+    lo = np.asarray(box[:3], np.float32)
+    hi = np.asarray(box[3:], np.float32)
+    ext = hi - lo
+    u = np.stack([uniform24(r[k]) for k in range(3)], axis=1)
+    p = (u * ext[None, :]) + lo[None, :]
+    return p.astype(np.float32), (p / np.float32(extent)).astype(np.float32)
 
 
 def training_pixels(seed: int, frame: int, batch: int, n_pix: int) -> np.ndarray:

@@ -243,3 +243,20 @@ def test_adam_first_step_closed_form():
     p, m, v = training.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.5, 0.9, 0.99, 1e-8)
     assert np.allclose(p, -0.5 * g / (np.abs(g) + 1e-8), rtol=1e-14, atol=0)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.01 * g * g)
+
+
+def test_world_points_uniform_in_the_box():
+    """World-space samples (Sec. 3.4): inside the box, uniform per axis, unit positions = p / extent."""
+    from oracle import philox
+    box = (0.5, 1.0, 2.0, 9.5, 4.0, 8.0)
+    p, u = philox.world_points(2, 3, 200000, box, 10.0)
+    lo, hi = np.array(box[:3]), np.array(box[3:])
+    assert np.all(p >= lo) and np.all(p < hi)
+    for k in range(3):
+        cnt, _ = np.histogram(p[:, k], bins=20, range=(lo[k], hi[k]))
+        chi2 = ((cnt - 10000.0) ** 2 / 10000.0).sum()
+        assert chi2 < 45.0                                       # 19 dof, p ~ 1e-3
+    assert np.array_equal(u, (p.astype(np.float64) / 10.0).astype(np.float32))
+    # the first coordinate is the uniform of the first Philox word of counter (i, frame, 6)
+    w = philox.philox4x32_10(philox._counter(np.arange(5, dtype=np.uint64), 3, 6), philox._key(2))[0]
+    assert np.allclose(p[:5, 0], lo[0] + philox.uniform24(w).astype(np.float64) * 9.0, rtol=1e-6)
