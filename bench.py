@@ -284,6 +284,7 @@ def main():
     from paper_2506_05930_amd import api
     from paper_2506_05930_amd.cache import NVCache
     from workloads import box_scene, get_workload, init_params
+    from workloads.scenes import SCENE_EXTENT
 
     over = {"mlp_dtype": args.dtype} if args.dtype else {}
     if args.loop and args.workload == "train_1080p":
@@ -332,6 +333,24 @@ def main():
             api.nvc_sample_wrs(vis, pos, nrm, lights, cache.vis_floor, cache.seed, frame, out["idx"], out["pmf"],
                                out["wsum"], out["di"], st)
 
+    nw = wl.world_batch
+    if nw:
+        wpos = torch.empty((nw, 3), dtype=torch.float32, device=dev)
+        wunit = torch.empty_like(wpos)
+        wlab = torch.empty((nw, wl.mlp.n_out), dtype=torch.uint8, device=dev)
+
+    def do_world(frame, st=None):
+        """The world-space half of the training batch: points, labels and gradients."""
+        if not nw:
+            return
+        api.nvc_world_samples(cache.seed, frame, wl.world_box, SCENE_EXTENT, wpos, wunit, st)
+        if clustered:
+            api.nvc_shadow_labels_clustered(wpos, None, lights, cache.cl_offsets, cache.cl_members, spheres,
+                                            cache.seed, frame, wlab, st)
+        else:
+            api.nvc_shadow_labels(wpos, None, lights, spheres, wlab, st)
+        cache.gradients(wunit, labels=wlab, batch=nw, stream=st)
+
     def do_labels(frame, st=None):
         if clustered:
             api.nvc_shadow_labels_clustered(pos, pix, lights, cache.cl_offsets, cache.cl_members, spheres, cache.seed,
@@ -349,6 +368,7 @@ def main():
             api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws, side)
             do_labels(frame, side)
             cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=side)
+            do_world(frame, side)
             if kev is not None:
                 kev[0].record(stream)
             api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis, stream)
@@ -370,6 +390,7 @@ def main():
         do_labels(frame)
         ev[4].record(stream)
         cache.gradients(pos_unit, labels=labels, pix=pix, batch=B)
+        do_world(frame)
         ev[5].record(stream)
         cache.adam()
         ev[6].record(stream)
@@ -451,7 +472,8 @@ def main():
         "dtype": wl.mlp.dtype,
         "data": "synthetic",
         "config": {"workload": wl.name, "pixels": n_pix, "lights": wl.n_lights, "spheres": wl.n_spheres,
-                   "train_batch": B, "grid": f"L{wl.grid.n_levels} F{wl.grid.n_feat} T2^{wl.grid.log2_T}",
+                   "train_batch": B, **({"world_batch": wl.world_batch} if wl.world_batch else {}),
+                   "grid": f"L{wl.grid.n_levels} F{wl.grid.n_feat} T2^{wl.grid.log2_T}",
                    "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}"},
         "ms_per_frame": ms_per_step,
         "streams": "training half on a second stream beside inference + WRS; stage_ms from a serial pass",

@@ -188,6 +188,18 @@ int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix);
 int nvc_select_pixels(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
                       int32_t* pix, void* workspace, int64_t workspace_bytes, void* stream);
 
+/* World-space training points (Sec. 3.4: training examples at random scene
+ * positions, which prepare the cache for views it has not seen yet; the
+ * paper mixes them with the screen-space ones).  Point i is, per axis,
+ * lo + u * (hi - lo) (FP32: the difference, then the product, then the sum)
+ * with u = (r >> 8) * 2^-24 from words 0, 1, 2 of Philox4x32-10 with counter
+ * (i lo32, i hi32, frame, 6) and key (seed lo32, seed hi32); pos_unit =
+ * p / extent (correctly rounded), the unit-cube position the encoding takes.
+ * box: HOST float [6] = lo xyz, hi xyz (lo <= hi, finite); extent > 0.
+ * pos_scene, pos_unit: float32 [n][3] device.  ctr as in nvc_select_pixels. */
+int nvc_world_samples(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n, const float* box,
+                      float extent, float* pos_scene, float* pos_unit, void* stream);
+
 /* Shadow-ray labels (Sec. 3.4: one shadow ray from each training point to
  * each light) against sphere occluders.  Sample b uses position
  * pos[pix[b]] (pix may be NULL: pos[b]); every pix[b] must index a row of

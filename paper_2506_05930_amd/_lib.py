@@ -28,7 +28,7 @@ EXPORTS = [
     "nvc_pack_mlp", "nvc_encode", "nvc_infer", "nvc_mlp_forward", "nvc_sample_wrs", "nvc_select_pixels_workspace_bytes",
     "nvc_select_pixels", "nvc_shadow_labels",
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
-    "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered",
+    "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered", "nvc_world_samples",
 ]
 
 
@@ -73,6 +73,8 @@ _SIGS = {
     "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_float, c_float,
                            c_int32, c_float, c_float, c_float, c_int32, c_void_p]),
     "nvc_counters_advance": (c_int32, [c_void_p, c_void_p]),
+    "nvc_world_samples": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_void_p, c_float, c_void_p, c_void_p,
+                                    c_void_p]),
     "nvc_cluster_lights": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),
     "nvc_shadow_labels_clustered": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p,
                                               c_int32, c_void_p, c_int32, c_uint64, c_uint32, c_void_p, c_void_p,

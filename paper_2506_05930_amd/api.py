@@ -191,6 +191,18 @@ def nvc_shadow_labels(pos: torch.Tensor, pix, lights: torch.Tensor, spheres: tor
                                                                   _stream(stream)))
 
 
+def nvc_world_samples(seed: int, frame: int, box, extent: float, pos_scene: torch.Tensor, pos_unit: torch.Tensor,
+                      stream=None, ctr=None) -> None:
+    """World-space training points uniform in box = (lo xyz, hi xyz), scene and unit-cube positions."""
+    n = pos_scene.shape[0]
+    ps = _ptr(pos_scene, "pos_scene", torch.float32, (n, 3))
+    pu = _ptr(pos_unit, "pos_unit", torch.float32, (n, 3))
+    b = (ctypes.c_float * 6)(*[float(x) for x in box])
+    _lib.check("nvc_world_samples", _lib.load().nvc_world_samples(int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF,
+                                                                  _counters(ctr), n, b, float(extent), ps, pu,
+                                                                  _stream(stream)))
+
+
 def nvc_cluster_lights(lights, k: int, iters: int = 20):
     """Host k-means of the lights (array-like [n][4] on the host) -> (offsets int32 [k+1], members int32 [n])."""
     arr = np.ascontiguousarray(np.asarray(lights.cpu() if isinstance(lights, torch.Tensor) else lights,

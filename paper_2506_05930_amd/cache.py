@@ -86,6 +86,13 @@ class NVCache:
         self.cl_members = torch.as_tensor(np.asarray(members, np.int32)).to(self.device)
         self.n_cand = int(n_cand)
 
+    def set_world_samples(self, n_world: int, box, extent: float):
+        """Add n_world world-space training points per step, uniform in box = (lo xyz, hi xyz) of the scene
+        (Sec. 3.4: the paper trains on 4096 world-space and 4096 screen-space samples); extent maps scene
+        positions to the unit cube (x / extent).  The two halves' gradients are added; with equal halves
+        that is twice the mean over the whole batch, a factor Adam does not see (up to eps)."""
+        self.world = (int(n_world), tuple(float(x) for x in box), float(extent))
+
     @property
     def clustered(self) -> bool:
         return getattr(self, "cl_offsets", None) is not None
@@ -161,6 +168,19 @@ class NVCache:
         else:
             api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
         self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
+        if getattr(self, "world", None) is not None and self.world[0] > 0:
+            nw, box, extent = self.world
+            if "wpos" not in bufs:
+                bufs["wpos"] = torch.empty((nw, 3), dtype=torch.float32, device=self.device)
+                bufs["wunit"] = torch.empty((nw, 3), dtype=torch.float32, device=self.device)
+                bufs["wlabels"] = torch.empty((nw, self.mlp.n_out), dtype=torch.uint8, device=self.device)
+            api.nvc_world_samples(self.seed, frame, box, extent, bufs["wpos"], bufs["wunit"], stream, ctr=ctr)
+            if self.clustered:
+                api.nvc_shadow_labels_clustered(bufs["wpos"], None, lights, self.cl_offsets, self.cl_members, spheres,
+                                                self.seed, frame, bufs["wlabels"], stream, ctr=ctr)
+            else:
+                api.nvc_shadow_labels(bufs["wpos"], None, lights, spheres, bufs["wlabels"], stream)
+            self.gradients(bufs["wunit"], labels=bufs["wlabels"], batch=nw, stream=stream)
         return bufs
 
     def train_step(self, pos_unit, pos_scene, lights, spheres, frame: int, batch: int, bufs: dict | None = None,

@@ -202,6 +202,18 @@ int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n, const flo
     return hip_status(launch_labels(pos, pix, n, lights, m, spheres, n_spheres, labels, (hipStream_t)stream));
 }
 
+int nvc_world_samples(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n, const float* box,
+                      float extent, float* pos_scene, float* pos_unit, void* stream) {
+    if (n < 0 || !(extent > 0.0f) || !isfinite(extent)) return NVC_ERR_SHAPE;
+    if (!box) return NVC_ERR_NULL;
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(box[k]) || !isfinite(box[k + 3]) || !(box[k] <= box[k + 3])) return NVC_ERR_SHAPE;
+    if (n == 0) return NVC_OK;
+    if (!pos_scene || !pos_unit) return NVC_ERR_NULL;
+    return hip_status(launch_world_samples(seed, frame, ctr ? &ctr->frame : nullptr, n, box, extent, pos_scene,
+                                           pos_unit, (hipStream_t)stream));
+}
+
 int nvc_cluster_lights(const float* lights, int32_t n_lights, int32_t k, int32_t iters, int32_t* offsets,
                        int32_t* members) {
     if (n_lights < 1 || k < 1 || k > 128 || k > n_lights || iters < 1) return NVC_ERR_SHAPE;

@@ -126,6 +126,37 @@ hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* f
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ world-space samples
+// Training points at random scene positions (not only on the visible
+// surfaces): p = lo + u * (hi - lo) per axis, u from words 0..2 of Philox
+// counter (i, frame, 6); unit-cube position p / extent.
+__global__ void world_samples_kernel(uint32_t k0, uint32_t k1, uint32_t frame, const uint32_t* __restrict__ frame_dev,
+                                     int64_t n, float lx, float ly, float lz, float hx, float hy, float hz,
+                                     float extent, float* __restrict__ pos_scene, float* __restrict__ pos_unit) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t fr = frame_dev ? *frame_dev : frame;
+    uint32_t w[4];
+    philox_words((uint32_t)i, (uint32_t)((uint64_t)i >> 32), fr, 6u, k0, k1, w);
+    const float lo[3] = {lx, ly, lz}, hi[3] = {hx, hy, hz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float u = (float)(w[k] >> 8) * 0x1.0p-24f;
+        const float p = u * (hi[k] - lo[k]) + lo[k];
+        pos_scene[i * 3 + k] = p;
+        pos_unit[i * 3 + k] = __fdiv_rn(p, extent);
+    }
+}
+
+hipError_t launch_world_samples(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n, const float* box,
+                                float extent, float* pos_scene, float* pos_unit, hipStream_t st) {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(world_samples_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t)seed, (uint32_t)(seed >> 32),
+                       frame, frame_dev, n, box[0], box[1], box[2], box[3], box[4], box[5], extent, pos_scene,
+                       pos_unit);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ shadow labels
 __device__ inline uint32_t float_key(float v) { return __float_as_uint(v); }   // order-preserving for v >= 0
 

@@ -81,6 +81,8 @@ int64_t select_pixels_workspace_bytes(int64_t n_pix);
 hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
                                 int64_t batch, int32_t* pix, void* workspace, hipStream_t st);
 size_t labels_smem_bytes(int m, int n_spheres);
+hipError_t launch_world_samples(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n, const float* box,
+                                float extent, float* pos_scene, float* pos_unit, hipStream_t st);
 hipError_t launch_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int m,
                          const float* spheres, int n_spheres, uint8_t* labels, hipStream_t st);
 bool train_supported(const GridHost& g, const NetShape& s);

@@ -138,6 +138,13 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_cluster_lights(P, 10, 11, 5, P, P) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_cluster_lights(P, 10, 0, 5, P, P) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_cluster_lights(None, 10, 4, 5, P, P) == _lib.NVC_ERR_NULL
+    box = (ctypes.c_float * 6)(0, 0, 0, 1, 1, 1)
+    bad = (ctypes.c_float * 6)(0, 2, 0, 1, 1, 1)
+    assert lib.nvc_world_samples(0, 0, N, 10, box, 0.0, P, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_world_samples(0, 0, N, 10, bad, 10.0, P, P, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_world_samples(0, 0, N, 10, None, 10.0, P, P, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_world_samples(0, 0, N, 10, box, 10.0, None, P, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_world_samples(0, 0, N, 0, box, 10.0, None, None, N) == 0
 
 
 def test_host_kmeans_equals_the_oracle():

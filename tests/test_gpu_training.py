@@ -133,3 +133,49 @@ def test_trained_clustered_cache_reduces_estimator_variance():
           f"relative mean error {bias_tr:.4f} / {bias_no:.4f}; loss {cache.loss_buf.item():.4f}")
     assert bias_tr < 0.02 and bias_no < 0.02
     assert ratio < 0.7 and share > 0.6
+
+
+def test_world_samples_match_oracle():
+    from oracle import philox
+    from paper_2506_05930_amd import api
+    box = (0.5, 0.25, 1.0, 9.5, 9.75, 9.0)
+    ps = torch.empty((100003, 3), dtype=torch.float32, device=DEV)
+    pu = torch.empty_like(ps)
+    api.nvc_world_samples(2, 7, box, 10.0, ps, pu)
+    rs, ru = philox.world_points(2, 7, 100003, box, 10.0)
+    assert np.array_equal(ps.cpu().numpy(), rs) and np.array_equal(pu.cpu().numpy(), ru)
+    c = api.new_counters(frame=7, device=DEV)
+    ps2 = torch.empty_like(ps)
+    api.nvc_world_samples(2, 0, box, 10.0, ps2, torch.empty_like(ps), ctr=c)
+    assert torch.equal(ps, ps2)
+
+
+def test_world_space_samples_teach_unseen_space():
+    """The paper's training mix (Sec. 3.4, Sec. 3.5 on unseen views): with half of the 8192 samples at random
+    scene positions, the cache predicts visibility away from the visible surfaces far better than when
+    trained on screen samples only, and about as well on the surfaces."""
+    wl = get_workload("paper_1080p")
+    sc = box_scene(0, 320, 180, 64, 32, 256)
+    p = init_params(1, wl.grid, wl.mlp, init=wl.init)
+    pos_unit, pos = t(sc["pos_unit"]), t(sc["pos"])
+    lights, spheres = t(sc["lights"]), t(sc["spheres"])
+    from oracle import philox
+    box = (0.5, 0.5, 0.5, 9.5, 9.5, 9.5)
+    wp, wu = philox.world_points(99, 0, 4096, box, 10.0)            # evaluation points (another seed)
+    Vw = shadow.labels_fp32(wp, sc["lights"], sc["spheres"]).astype(np.float64)
+    sub = np.random.default_rng(5).choice(sc["pos"].shape[0], 4096, replace=False)
+    Vs = shadow.labels_fp32(sc["pos"][sub], sc["lights"], sc["spheres"]).astype(np.float64)
+    err = {}
+    for mix in (False, True):
+        cache = make_cache(wl, p)
+        if mix:
+            cache.set_world_samples(4096, box, 10.0)
+        for frame in range(200):
+            cache.train_step(pos_unit, pos, lights, spheres, frame, 4096 if mix else 8192)
+        vw = cache.infer(t(wu), dtype=torch.float32).cpu().numpy()
+        vs = cache.infer(t(sc["pos_unit"][sub]), dtype=torch.float32).cpu().numpy()
+        err[mix] = (np.abs(vw - Vw).mean(), np.abs(vs - Vs).mean())
+    print(f"visibility MAE off the surfaces: screen only {err[False][0]:.3f}, mix {err[True][0]:.3f}; "
+          f"on the surfaces: {err[False][1]:.3f}, {err[True][1]:.3f}")
+    assert err[True][0] < 0.7 * err[False][0]
+    assert err[True][1] < 2.0 * err[False][1] + 0.01

@@ -89,6 +89,8 @@ class Workload:
     init: str = "xavier"         # MLP initialisation: 'xavier' or 'he' (Sec. 3.4)
     n_clusters: int = 0          # clustered cache (Sec. 3.6): one output per cluster of lights (0: per light)
     n_cand: int = 8              # RIS candidates of the clustered pick
+    world_batch: int = 0         # world-space training points per step besides train_batch screen samples
+    world_box: tuple = (0.5, 0.5, 0.5, 9.5, 9.5, 9.5)   # where they are drawn (scene units)
     beta1: float = 0.9
     beta2: float = 0.99
     adam_eps: float = 1e-8
@@ -140,10 +142,11 @@ WORKLOADS = {
         grid=GridCfg(n_levels=10, n_feat=4, log2_T=14, base_res=16, growth=1.19),
         mlp=MlpCfg(n_in=40, width=32, n_hidden=2, n_out=32, act="leaky", leaky_slope=0.01, dtype="f16"),
         kind="boxes", width=1920, height=1080, n_boxes=64, n_lights=32, n_spheres=256,
-        train_batch=8192, loss="l2", lr=0.05, lr_end=0.001, lr_decay_steps=200, init="he",
+        train_batch=4096, world_batch=4096, loss="l2", lr=0.05, lr_end=0.001, lr_decay_steps=200, init="he",
         notes="the paper's own configuration (Sec. 3.3-3.4): ten levels x four features at base 16 (T = 2^14, "
               "growth 1.19), 40-32-32-32 MLP with leaky ReLU 0.01, L2 loss, He init, Adam with the rate lowered "
-              "linearly from 0.05 to 0.001 over the first 200 steps, 8192 screen samples per frame; 1080p box scene",
+              "linearly from 0.05 to 0.001 over the first 200 steps, 4096 screen + 4096 world-space samples per "
+              "frame; 1080p box scene",
     ),
     "clustered_1080p": Workload(
         name="clustered_1080p",
