@@ -135,6 +135,19 @@ int nvc_infer(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, cons
 int nvc_mlp_forward(const nvc_mlp* mlp, const void* packed, const void* enc, int32_t enc_dtype, int64_t n,
                     void* vis, int32_t vis_dtype, void* stream);
 
+/* A pick as a reservoir of resampled importance sampling for the target
+ * function f (the unshadowed weight), the form in which ReSTIR takes its
+ * initial candidates (Sec. 4.2: the clustered cache generates a reservoir):
+ * y the light (-1: none), M the number of candidates it was resampled from,
+ * w_sum the sum of their resampling weights, W = w_sum / (M f_y) the
+ * unbiased contribution weight (f_y V_y W estimates sum_i f_i V_i). */
+typedef struct nvc_reservoir {
+    int32_t y;
+    int32_t M;
+    float w_sum;
+    float W;
+} nvc_reservoir;
+
 /* Per-frame counters in DEVICE memory, for frames recorded once into a HIP
  * graph and replayed: nvc_sample_wrs and nvc_select_pixels given a non-NULL
  * `ctr` take the frame number from ctr->frame, and nvc_adam takes its step
@@ -165,11 +178,18 @@ int nvc_counters_advance(nvc_counters* ctr, void* stream);
  * light order and W = C_{m-1}: idx = the first i with C_i > u * W.
  * Outputs (float32 / int32 [n]): idx (-1 when W = 0), pmf = w_idx / W (0 when
  * W = 0), wsum = W, and, if di != NULL, di = sum_i v_i f_i / pi (raw v).
- * ctr (device, or NULL): if given, frame = ctr->frame at run time. */
+ * ctr (device, or NULL): if given, frame = ctr->frame at run time.
+ * mask (uint8 [n], or NULL): pixels with mask 0 are skipped (the cache is
+ * run only where needed, e.g. where a screen-space reuse lost its history):
+ * idx = -1, pmf = wsum = di = 0, an empty reservoir.
+ * res (nvc_reservoir [n], or NULL): the pick as a one-candidate reservoir
+ * for target f: y = idx, M = 1, W = W / w_idx (= 1 / pmf, FP32 division),
+ * w_sum = f_idx * W; {-1, 0, 0, 0} without a pick. */
 int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m,
                    const float* pos, const float* nrm, const float* lights, float vis_floor,
                    uint64_t seed, uint32_t frame, const nvc_counters* ctr,
-                   int32_t* idx, float* pmf, float* wsum, float* di, void* stream);
+                   int32_t* idx, float* pmf, float* wsum, float* di, const uint8_t* mask, nvc_reservoir* res,
+                   void* stream);
 
 /* Host only.  Workspace bytes nvc_select_pixels needs for an image of n_pix pixels. */
 int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix);
@@ -271,11 +291,15 @@ int nvc_shadow_labels_clustered(const float* pos, const int32_t* pix, int64_t n,
  * so that f_x V_x weight is an unbiased estimate of sum_i f_i V_i.
  * Outputs [n]: idx (int32, the light, -1 if W = 0 or S = 0), weight (float32,
  * 0 then), cluster (int32 y or -1; may be NULL).  1 <= k <= 128,
- * 1 <= n_cand <= 64; ctr as in nvc_sample_wrs. */
+ * 1 <= n_cand <= 64; ctr and mask as in nvc_sample_wrs.
+ * res (or NULL): the RIS reservoir, y = idx, M = n_cand, W = weight,
+ * w_sum = (S * fl(m_y)) / P, the sum of the candidates' resampling weights
+ * f_k / (P / m_y); {-1, 0, 0, 0} without a pick. */
 int nvc_sample_clustered(const void* vis, int32_t vis_dtype, int64_t n, int32_t k, const float* pos,
                          const float* nrm, const float* lights, int32_t n_lights, const int32_t* offsets,
                          const int32_t* members, float vis_floor, int32_t n_cand, uint64_t seed, uint32_t frame,
-                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster, void* stream);
+                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster,
+                         const uint8_t* mask, nvc_reservoir* res, void* stream);
 
 /* Host only.  Workspace bytes nvc_train_step needs for this network and batch. */
 int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch);

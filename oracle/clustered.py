@@ -160,7 +160,8 @@ def sample(vis, pos, nrm, lights, offsets, members, seed: int, frame: int, n_can
     my = sizes[np.where(y >= 0, y, 0)].astype(dtype)
     with np.errstate(invalid="ignore", divide="ignore"):
         W = np.where(ok, (S * my) / ((dt(n_cand) * P) * fx), dt(0)).astype(dtype)
-    return {"idx": idx, "cluster": np.where(ok, y, -1).astype(np.int64), "W": W,
+        w_sum = np.where(ok, (S * my) / P, dt(0)).astype(dtype)    # sum of the resampling weights f_k m_y / P
+    return {"idx": idx, "cluster": np.where(ok, y, -1).astype(np.int64), "W": W, "w_sum": w_sum,
             "P": np.where(y >= 0, P, dt(0))}
 
 

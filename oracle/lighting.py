@@ -91,6 +91,22 @@ def wrs_pick(w: np.ndarray, u: np.ndarray):
     return idx, pmf, W
 
 
+def pick_reservoir(w, f, idx, W):
+    """The pick as a one-candidate reservoir for the target f (Sec. 4.2: the cache's pick can seed ReSTIR):
+    y = idx, M = 1, contribution weight W_r = W / w_idx (= 1 / pmf), w_sum = f_idx * W_r, in w's dtype;
+    (-1, 0, 0, 0) without a pick."""
+    w = np.asarray(w)
+    dt = w.dtype.type
+    safe = np.where(idx >= 0, idx, 0)
+    wsel = np.take_along_axis(w, safe[:, None], axis=1)[:, 0]
+    fsel = np.take_along_axis(np.asarray(f).astype(w.dtype), safe[:, None], axis=1)[:, 0]
+    ok = idx >= 0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        Wr = np.where(ok, np.asarray(W).astype(w.dtype) / np.where(ok, wsel, dt(1)), dt(0)).astype(w.dtype)
+    return {"y": np.where(ok, idx, -1), "M": ok.astype(np.int32), "w_sum": np.where(ok, fsel * Wr, dt(0)),
+            "W": Wr}
+
+
 def selection_pmf(w: np.ndarray) -> np.ndarray:
     """Full selection distribution p_i = w_i / sum_j w_j (FP64), zero rows stay zero."""
     w = np.asarray(w, np.float64)

@@ -60,7 +60,8 @@ _SIGS = {
                             c_int32, c_void_p]),
     "nvc_mlp_forward": (c_int32, [POINTER(NvcMlp), c_void_p, c_void_p, c_int32, c_int64, c_void_p, c_int32, c_void_p]),
     "nvc_sample_wrs": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_float,
-                                 c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+                                 c_uint64, c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p]),
     "nvc_select_pixels_workspace_bytes": (c_int64, [c_int64]),
     "nvc_select_pixels": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_int64,
                                     c_void_p]),
@@ -81,7 +82,7 @@ _SIGS = {
                                               c_void_p]),
     "nvc_sample_clustered": (c_int32, [c_void_p, c_int32, c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                        c_void_p, c_void_p, c_float, c_int32, c_uint64, c_uint32, c_void_p, c_void_p,
-                                       c_void_p, c_void_p, c_void_p]),
+                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
 }
 
 _lib = None

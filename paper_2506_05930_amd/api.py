@@ -146,7 +146,9 @@ def nvc_mlp_forward(mlp: NvcMlp, packed: torch.Tensor, enc: torch.Tensor, vis: t
 
 def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, vis_floor: float, seed: int,
                    frame: int, idx: torch.Tensor, pmf: torch.Tensor, wsum: torch.Tensor, di=None,
-                   stream=None, ctr=None) -> None:
+                   stream=None, ctr=None, mask=None, res=None) -> None:
+    """mask: uint8 [n] (0 = skip the pixel) or None; res: a 4-byte tensor [n][4] receiving nvc_reservoir
+    records (int32 y, int32 M, float32 w_sum, float32 W) or None."""
     n, m = vis.shape
     pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16))
     pp = _ptr(pos, "pos", torch.float32, (n, 3))
@@ -156,10 +158,12 @@ def nvc_sample_wrs(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tens
     pm = _ptr(pmf, "pmf", torch.float32, (n,))
     pw = _ptr(wsum, "wsum", torch.float32, (n,))
     pd = _ptr(di, "di", torch.float32, (n,), optional=True)
+    pk = _ptr(mask, "mask", torch.uint8, (n,), optional=True)
+    pr = _ptr(res, "res", (torch.int32, torch.float32), (n, 4), optional=True)
     _lib.check("nvc_sample_wrs", _lib.load().nvc_sample_wrs(pv, _DT_CODE[vis.dtype], n, m, pp, pn, pl,
                                                             float(vis_floor), int(seed) & (2 ** 64 - 1),
                                                             int(frame) & 0xFFFFFFFF, _counters(ctr), pi, pm, pw,
-                                                            pd, _stream(stream)))
+                                                            pd, pk, pr, _stream(stream)))
 
 
 def nvc_select_pixels_workspace_bytes(n_pix: int) -> int:
@@ -237,7 +241,8 @@ def nvc_shadow_labels_clustered(pos: torch.Tensor, pix, lights: torch.Tensor, of
 
 def nvc_sample_clustered(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torch.Tensor, offsets: torch.Tensor,
                          members: torch.Tensor, vis_floor: float, n_cand: int, seed: int, frame: int,
-                         idx: torch.Tensor, weight: torch.Tensor, cluster=None, stream=None, ctr=None) -> None:
+                         idx: torch.Tensor, weight: torch.Tensor, cluster=None, stream=None, ctr=None, mask=None,
+                         res=None) -> None:
     n, k = vis.shape
     pv = _ptr(vis, "vis", (torch.float32, torch.float16, torch.bfloat16))
     pp = _ptr(pos, "pos", torch.float32, (n, 3))
@@ -248,9 +253,11 @@ def nvc_sample_clustered(vis: torch.Tensor, pos: torch.Tensor, nrm, lights: torc
     pi = _ptr(idx, "idx", torch.int32, (n,))
     pw = _ptr(weight, "weight", torch.float32, (n,))
     pc = _ptr(cluster, "cluster", torch.int32, (n,), optional=True)
+    pk = _ptr(mask, "mask", torch.uint8, (n,), optional=True)
+    pr = _ptr(res, "res", (torch.int32, torch.float32), (n, 4), optional=True)
     _lib.check("nvc_sample_clustered", _lib.load().nvc_sample_clustered(
         pv, _DT_CODE[vis.dtype], n, k, pp, pn, pl, lights.shape[0], po, pm, float(vis_floor), int(n_cand),
-        int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, _counters(ctr), pi, pw, pc, _stream(stream)))
+        int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, _counters(ctr), pi, pw, pc, pk, pr, _stream(stream)))
 
 
 def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor, pix,

@@ -168,14 +168,15 @@ int nvc_mlp_forward(const nvc_mlp* mlp, const void* packed, const void* enc, int
 
 int nvc_sample_wrs(const void* vis, int32_t vis_dtype, int64_t n, int32_t m, const float* pos, const float* nrm,
                    const float* lights, float vis_floor, uint64_t seed, uint32_t frame, const nvc_counters* ctr,
-                   int32_t* idx, float* pmf, float* wsum, float* di, void* stream) {
+                   int32_t* idx, float* pmf, float* wsum, float* di, const uint8_t* mask, nvc_reservoir* res,
+                   void* stream) {
     if (!valid_dtype(vis_dtype)) return NVC_ERR_DTYPE;
     if (n < 0 || m < 1 || m > 128) return NVC_ERR_SHAPE;
     if (!(vis_floor >= 0.0f) || !isfinite(vis_floor)) return NVC_ERR_SHAPE;
     if (n == 0) return NVC_OK;
     if (!vis || !pos || !lights || !idx || !pmf || !wsum) return NVC_ERR_NULL;
     return hip_status(launch_wrs(vis, vis_dtype, n, m, pos, nrm, lights, vis_floor, seed, frame,
-                                 ctr ? &ctr->frame : nullptr, idx, pmf, wsum, di, (hipStream_t)stream));
+                                 ctr ? &ctr->frame : nullptr, idx, pmf, wsum, di, mask, res, (hipStream_t)stream));
 }
 
 int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix) {
@@ -240,7 +241,8 @@ int nvc_shadow_labels_clustered(const float* pos, const int32_t* pix, int64_t n,
 int nvc_sample_clustered(const void* vis, int32_t vis_dtype, int64_t n, int32_t k, const float* pos,
                          const float* nrm, const float* lights, int32_t n_lights, const int32_t* offsets,
                          const int32_t* members, float vis_floor, int32_t n_cand, uint64_t seed, uint32_t frame,
-                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster, void* stream) {
+                         const nvc_counters* ctr, int32_t* idx, float* weight, int32_t* cluster,
+                         const uint8_t* mask, nvc_reservoir* res, void* stream) {
     if (n < 0 || k < 1 || k > 128 || n_lights < 0 || n_cand < 1 || n_cand > 64) return NVC_ERR_SHAPE;
     if (vis_dtype != NVC_F32 && vis_dtype != NVC_F16 && vis_dtype != NVC_BF16) return NVC_ERR_DTYPE;
     if (!(vis_floor >= 0.0f) || !isfinite(vis_floor)) return NVC_ERR_SHAPE;
@@ -248,7 +250,7 @@ int nvc_sample_clustered(const void* vis, int32_t vis_dtype, int64_t n, int32_t 
     if (!vis || !pos || !offsets || !idx || !weight || (n_lights > 0 && (!lights || !members))) return NVC_ERR_NULL;
     return hip_status(launch_clustered_sample(vis, vis_dtype, n, k, pos, nrm, lights, n_lights, offsets, members,
                                               vis_floor, n_cand, seed, frame, ctr ? &ctr->frame : nullptr, idx,
-                                              weight, cluster, (hipStream_t)stream));
+                                              weight, cluster, mask, res, (hipStream_t)stream));
 }
 
 int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch) {

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
     const float* __restrict__ lights, int n_lights, const int32_t* __restrict__ offsets,
     const int32_t* __restrict__ members, float vis_floor, int n_cand, uint32_t k0, uint32_t k1, uint32_t frame,
     const uint32_t* __restrict__ frame_dev, int32_t* __restrict__ idx_out, float* __restrict__ weight_out,
-    int32_t* __restrict__ cluster_out) {
+    int32_t* __restrict__ cluster_out, const uint8_t* __restrict__ mask, nvc_reservoir* __restrict__ res) {
     __shared__ int off0[128];
     __shared__ int msize[128];
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
@@ -129,6 +129,13 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    if (mask && mask[p] == 0) {                 // not needed at this pixel: an empty result
+        idx_out[p] = -1;
+        weight_out[p] = 0.0f;
+        if (cluster_out) cluster_out[p] = -1;
+        if (res) res[p] = nvc_reservoir{-1, 0, 0.0f, 0.0f};
+        return;
+    }
     const uint32_t fr = frame_dev ? *frame_dev : frame;
     const uint32_t plo = (uint32_t)p, phi = (uint32_t)((uint64_t)p >> 32);
     const VT* row = vis + p * (int64_t)k;
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
         }
     }
     int pick = -1, cl = -1;
-    float Wx = 0.0f;
+    float Wx = 0.0f, wsum_r = 0.0f;
     if (y >= 0) {
         const float P = __fdiv_rn(wy, W);
         const int o0 = off0[y], m = msize[y];
@@ -234,11 +241,13 @@ __global__ __launch_bounds__(kClSampleThreads) void clustered_sample_kernel(
             }
             cl = y;
             Wx = __fdiv_rn(Ssum * (float)m, ((float)n_cand * P) * fx);
+            wsum_r = __fdiv_rn(Ssum * (float)m, P);
         }
     }
     idx_out[p] = pick;
     weight_out[p] = Wx;
     if (cluster_out) cluster_out[p] = cl;
+    if (res) res[p] = nvc_reservoir{pick, pick >= 0 ? n_cand : 0, pick >= 0 ? wsum_r : 0.0f, Wx};
 }
 
 // ------------------------------------------------------------------ host
@@ -263,13 +272,13 @@ hipError_t launch_clustered_sample(const void* vis, int vis_dtype, int64_t n, in
                                    const float* lights, int n_lights, const int32_t* offsets, const int32_t* members,
                                    float vis_floor, int n_cand, uint64_t seed, uint32_t frame,
                                    const uint32_t* frame_dev, int32_t* idx, float* weight, int32_t* cluster,
-                                   hipStream_t st) {
+                                   const uint8_t* mask, nvc_reservoir* res, hipStream_t st) {
     const unsigned blocks = (unsigned)((n + kClSampleThreads - 1) / kClSampleThreads);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     auto go = [&](auto kern, const void* v) {
         hipLaunchKernelGGL(kern, dim3(blocks), dim3(kClSampleThreads), 0, st,
                            reinterpret_cast<decltype(kern_vis_type(kern))>(v), n, k, pos, nrm, lights, n_lights, offsets,
-                           members, vis_floor, n_cand, k0, k1, frame, frame_dev, idx, weight, cluster);
+                           members, vis_floor, n_cand, k0, k1, frame, frame_dev, idx, weight, cluster, mask, res);
     };
     const bool c8 = n_cand == 8;
     if (vis_dtype == DT_F32)

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include "nvc.h"
+
 namespace nvc {
 
 constexpr int DT_F32 = 0;
@@ -76,7 +78,8 @@ hipError_t launch_mlp_forward(const NetShape& s, const PackPlan& plan, const voi
                               int enc_dtype, int64_t n, void* vis, int vis_dtype, hipStream_t st);
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
                       const float* lights, float vis_floor, uint64_t seed, uint32_t frame,
-                      const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st);
+                      const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di,
+                      const uint8_t* mask, nvc_reservoir* res, hipStream_t st);
 int64_t select_pixels_workspace_bytes(int64_t n_pix);
 hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
                                 int64_t batch, int32_t* pix, void* workspace, hipStream_t st);
@@ -102,7 +105,7 @@ hipError_t launch_clustered_sample(const void* vis, int vis_dtype, int64_t n, in
                                    const float* lights, int n_lights, const int32_t* offsets, const int32_t* members,
                                    float vis_floor, int n_cand, uint64_t seed, uint32_t frame,
                                    const uint32_t* frame_dev, int32_t* idx, float* weight, int32_t* cluster,
-                                   hipStream_t st);
+                                   const uint8_t* mask, nvc_reservoir* res, hipStream_t st);
 void cluster_lights_host(const float* lights, int n, int k, int iters, int32_t* offsets, int32_t* members);
 // frame += 1, step += 1 of the device counters {uint32 frame; int32 step}.
 hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st);

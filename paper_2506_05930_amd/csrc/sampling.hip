@@ -53,7 +53,9 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
                                                          uint32_t k0, uint32_t k1, uint32_t frame,
                                                          const uint32_t* __restrict__ frame_dev, int vec,
                                                          int32_t* __restrict__ idx_out, float* __restrict__ pmf_out,
-                                                         float* __restrict__ wsum_out, float* __restrict__ di_out) {
+                                                         float* __restrict__ wsum_out, float* __restrict__ di_out,
+                                                         const uint8_t* __restrict__ mask,
+                                                         nvc_reservoir* __restrict__ res) {
     __shared__ float4 L[128];
     __shared__ float cend[16][kWrsThreads];       // running sum at the end of each group of 8 lights
     for (int i = threadIdx.x; i < m; i += blockDim.x)
@@ -61,6 +63,14 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    if (mask && mask[p] == 0) {                 // not needed at this pixel: an empty result
+        idx_out[p] = -1;
+        pmf_out[p] = 0.0f;
+        wsum_out[p] = 0.0f;
+        if (di_out) di_out[p] = 0.0f;
+        if (res) res[p] = nvc_reservoir{-1, 0, 0.0f, 0.0f};
+        return;
+    }
     const int tid = threadIdx.x;
     const float px = pos[p * 3 + 0], py = pos[p * 3 + 1], pz = pos[p * 3 + 2];
     float nx = 0.f, ny = 0.f, nz = 0.f;
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
     }
     const VT* row = vis + p * (int64_t)m;
     const int ng = (m + 7) / 8;
-    float W = 0.0f, di = 0.0f, wlast = 0.0f;
+    float W = 0.0f, di = 0.0f, wlast = 0.0f, flast = 0.0f;
     int last_pos = -1;
     for (int g = 0; g < ng; ++g) {
         float v[8];
@@ -88,6 +98,7 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
                 if (w > 0.0f) {
                     last_pos = i;
                     wlast = w;
+                    flast = f;
                 }
             }
         }
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
     const float u = (float)(r0 >> 8) * 0x1.0p-24f;
     const float t = u * W;
     int pick = -1;
-    float wsel = 0.0f;
+    float wsel = 0.0f, fsel = 0.0f;
     int gs = -1;
     float c0 = 0.0f;
     for (int g = 0; g < ng; ++g) {
@@ -123,6 +134,7 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
                 if (pick < 0 && C > t) {
                     pick = i;
                     wsel = w;
+                    fsel = f;
                 }
             }
         }
@@ -130,35 +142,45 @@ __global__ __launch_bounds__(kWrsThreads) void wrs_kernel(const VT* __restrict__
     if (pick < 0 && last_pos >= 0) {          // only through rounding
         pick = last_pos;
         wsel = wlast;
+        fsel = flast;
     }
     if (!(W > 0.0f)) pick = -1;
     idx_out[p] = pick;
     pmf_out[p] = pick >= 0 ? __fdiv_rn(wsel, W) : 0.0f;
     wsum_out[p] = W;
     if (di_out) di_out[p] = di * 0.318309886183790672f;    // 1/pi
+    if (res) {
+        // One candidate drawn with probability pmf, for a target f: M = 1, W = 1/pmf, w_sum = f W.
+        const float Wr = pick >= 0 ? __fdiv_rn(W, wsel) : 0.0f;
+        res[p] = nvc_reservoir{pick, pick >= 0 ? 1 : 0, fsel * Wr, Wr};
+    }
 }
 
 template <typename VT>
 static void run_wrs(const VT* vis, int64_t n, int m, const float* pos, const float* nrm, const float* lights,
                     float vis_floor, uint32_t k0, uint32_t k1, uint32_t frame, const uint32_t* frame_dev,
-                    int32_t* idx, float* pmf, float* wsum, float* di, hipStream_t st) {
+                    int32_t* idx, float* pmf, float* wsum, float* di, const uint8_t* mask, nvc_reservoir* res,
+                    hipStream_t st) {
     const unsigned blocks = (unsigned)((n + kWrsThreads - 1) / kWrsThreads);
     const int vec = m % 8 == 0 && ((uintptr_t)vis & 15u) == 0;
     wrs_kernel<VT><<<blocks, kWrsThreads, 0, st>>>(vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev,
-                                                    vec, idx, pmf, wsum, di);
+                                                    vec, idx, pmf, wsum, di, mask, res);
 }
 
 hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const float* pos, const float* nrm,
                       const float* lights, float vis_floor, uint64_t seed, uint32_t frame,
                       const uint32_t* frame_dev, int32_t* idx, float* pmf, float* wsum, float* di,
-                      hipStream_t st) {
+                      const uint8_t* mask, nvc_reservoir* res, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (vis_dtype == DT_F32)
-        run_wrs((const float*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
+        run_wrs((const float*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, mask,
+                res, st);
     else if (vis_dtype == DT_F16)
-        run_wrs((const _Float16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
+        run_wrs((const _Float16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, mask,
+                res, st);
     else
-        run_wrs((const __bf16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, st);
+        run_wrs((const __bf16*)vis, n, m, pos, nrm, lights, vis_floor, k0, k1, frame, frame_dev, idx, pmf, wsum, di, mask,
+                res, st);
     return hipGetLastError();
 }
 

@@ -100,11 +100,11 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_infer(gg, ctypes.byref(m(width=48)), P, P, P, 10, P, 1, N) == _lib.NVC_ERR_UNSUPPORTED
     assert lib.nvc_infer(gg, mm, None, P, P, 10, P, 1, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_infer(gg, mm, None, None, None, 0, None, 1, N) == 0
-    assert lib.nvc_sample_wrs(P, 1, 10, 0, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 129, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_NULL
-    assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N) == _lib.NVC_ERR_DTYPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 0, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 129, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, P, N, P, -1.0, 0, 0, N, P, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_sample_wrs(P, 1, 10, 32, None, N, P, 1e-3, 0, 0, N, P, P, P, N, N, N, N) == _lib.NVC_ERR_NULL
+    assert lib.nvc_sample_wrs(P, 5, 10, 32, P, N, P, 1e-3, 0, 0, N, P, P, P, N, N, N, N) == _lib.NVC_ERR_DTYPE
     ws = lib.nvc_select_pixels_workspace_bytes(100)
     assert ws >= 800
     assert lib.nvc_select_pixels_workspace_bytes(0) == _lib.NVC_ERR_SHAPE
@@ -126,15 +126,16 @@ def test_calls_reject_bad_arguments_before_launching(lib):
     assert lib.nvc_adam(P, P, P, P, 10, 1, N, 5e-2, float("nan"), 200, 0.9, 0.99, 1e-8, 0, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_counters_advance(None, N) == _lib.NVC_ERR_NULL
     # clustered cache
+    sc = lib.nvc_sample_clustered
     assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, P, P, 0, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, P, P, 129, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_shadow_labels_clustered(P, N, 10, P, 100, None, P, 32, P, 16, 0, 0, N, P, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_shadow_labels_clustered(P, N, 0, P, 100, P, P, 32, P, 16, 0, 0, N, P, N) == 0
-    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 0, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 65, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, -1.0, 8, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_SHAPE
-    assert lib.nvc_sample_clustered(P, 7, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, P, P, N, N) == _lib.NVC_ERR_DTYPE
-    assert lib.nvc_sample_clustered(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, None, P, N, N) == _lib.NVC_ERR_NULL
+    assert sc(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 0, 0, 0, N, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert sc(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 65, 0, 0, N, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert sc(P, 1, 10, 32, P, N, P, 100, P, P, -1.0, 8, 0, 0, N, P, P, N, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert sc(P, 7, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, P, P, N, N, N, N) == _lib.NVC_ERR_DTYPE
+    assert sc(P, 1, 10, 32, P, N, P, 100, P, P, 1e-3, 8, 0, 0, N, None, P, N, N, N, N) == _lib.NVC_ERR_NULL
     assert lib.nvc_cluster_lights(P, 10, 11, 5, P, P) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_cluster_lights(P, 10, 0, 5, P, P) == _lib.NVC_ERR_SHAPE
     assert lib.nvc_cluster_lights(None, 10, 4, 5, P, P) == _lib.NVC_ERR_NULL

@@ -123,3 +123,73 @@ def test_clustered_sample_is_unbiased_on_the_gpu(scene):
     print(f"mean {est.mean():.6g} exact {mu:.6g} se {se:.3g}")
     assert mu > 0 and ((f > 0) & (V > 0)).sum() >= 20
     assert abs(est.mean() - mu) <= 4.5 * se
+
+
+def test_plain_pick_reservoir_and_mask(scene):
+    """nvc_sample_wrs: the reservoir of the pick (Sec. 4.2) bit-exact against the oracle; masked pixels give an
+    empty result and leave the others unchanged."""
+    from paper_2506_05930_amd import api
+    rng = np.random.default_rng(21)
+    n, m = 5001, 32
+    sel = rng.choice(scene["pos"].shape[0], n, replace=False)
+    pos, nrm = scene["pos"][sel], scene["nrm"][sel]
+    lights = scene["lights"][:m]
+    vis = t(rng.uniform(0, 1, (n, m)).astype(np.float32)).half()
+    outs = {}
+    for masked in (False, True):
+        mk = t((rng.uniform(size=n) > 0.3).astype(np.uint8)) if masked else None
+        o = {k: torch.empty(n, dtype=d, device=DEV) for k, d in
+             (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
+        res = torch.empty((n, 4), dtype=torch.int32, device=DEV)
+        api.nvc_sample_wrs(vis, t(pos), t(nrm), t(lights), 1e-3, 2, 3, o["idx"], o["pmf"], o["wsum"], o["di"],
+                           mask=mk, res=res)
+        outs[masked] = (o, res, mk)
+    o, res, _ = outs[False]
+    v32 = vis.float().cpu().numpy()
+    w = lighting.light_weights(pos, nrm, lights, v32, 1e-3, np.float32)
+    f = lighting.unshadowed_weight(pos, nrm, lights, np.float32)
+    idx, pmf, W = lighting.wrs_pick(w, philox.wrs_uniforms(2, 3, n))
+    ref = lighting.pick_reservoir(w, f, idx, W)
+    r = res.cpu()
+    assert np.array_equal(r[:, 0].numpy(), ref["y"]) and np.array_equal(r[:, 1].numpy(), ref["M"])
+    assert np.array_equal(r[:, 2].view(torch.float32).numpy(), ref["w_sum"])
+    assert np.array_equal(r[:, 3].view(torch.float32).numpy(), ref["W"])
+    o2, res2, mk = outs[True]
+    keep = mk.cpu().numpy().astype(bool)
+    for k in o:
+        a, b = o[k].cpu().numpy(), o2[k].cpu().numpy()
+        assert np.array_equal(a[keep], b[keep]) and np.all(b[~keep] == (-1 if k == "idx" else 0))
+    r2 = res2.cpu().numpy()
+    assert np.array_equal(r2[keep], r.numpy()[keep]) and np.all(r2[~keep] == [-1, 0, 0, 0])
+
+
+def test_clustered_pick_reservoir_and_mask(scene):
+    from paper_2506_05930_amd import api
+    k = 32
+    off, mem = random_partition(17, scene["lights"].shape[0], k)
+    rng = np.random.default_rng(22)
+    n = 4099
+    sel = rng.choice(scene["pos"].shape[0], n, replace=False)
+    pos, nrm = scene["pos"][sel], scene["nrm"][sel]
+    vis = t(rng.uniform(0, 1, (n, k)).astype(np.float32))
+    mk = t((rng.uniform(size=n) > 0.5).astype(np.uint8))
+    runs = []
+    for mask in (None, mk):
+        idx = torch.empty(n, dtype=torch.int32, device=DEV)
+        w = torch.empty(n, dtype=torch.float32, device=DEV)
+        res = torch.empty((n, 4), dtype=torch.float32, device=DEV)
+        api.nvc_sample_clustered(vis, t(pos), t(nrm), t(scene["lights"]), t(off), t(mem), 1e-3, 8, 2, 6, idx, w,
+                                 mask=mask, res=res)
+        runs.append((idx.cpu().numpy(), w.cpu().numpy(), res.cpu()))
+    ref = clustered.sample(vis.cpu().numpy(), pos, nrm, scene["lights"], off, mem, 2, 6, 8, dtype=np.float32)
+    idx, w, res = runs[0]
+    ok = ref["idx"] >= 0
+    assert np.array_equal(res[:, 0].view(torch.int32).numpy(), ref["idx"])
+    assert np.array_equal(res[:, 1].view(torch.int32).numpy(), np.where(ok, 8, 0))
+    assert np.array_equal(res[:, 2].numpy(), ref["w_sum"]) and np.array_equal(res[:, 3].numpy(), ref["W"])
+    keep = mk.cpu().numpy().astype(bool)
+    idx2, w2, res2 = runs[1]
+    assert np.array_equal(idx2[keep], idx[keep]) and np.all(idx2[~keep] == -1) and np.all(w2[~keep] == 0)
+    kk = torch.as_tensor(keep)
+    assert torch.equal(res2.view(torch.int32)[kk], res.view(torch.int32)[kk])      # bit patterns (y = -1 is a NaN)
+    assert np.all(res2[torch.as_tensor(~keep)].view(torch.int32).numpy()[:, :2] == [-1, 0])

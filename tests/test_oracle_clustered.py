@@ -131,3 +131,26 @@ def test_sample_mean_matches_the_exact_sum(n_cand):
     mu = (f * V).sum()
     se = est.std() / np.sqrt(n)
     assert abs(est.mean() - mu) <= 4.5 * se
+
+
+def test_reservoirs_are_consistent():
+    """Both picks as reservoirs (Sec. 4.2): W = w_sum / (M f_y), and W * P(pick) = 1 for the plain pick."""
+    rng = np.random.default_rng(4)
+    n, m = 3000, 32
+    f = rng.uniform(0.0, 2.0, (n, m)).astype(np.float32)
+    f[:, ::5] = 0
+    v = rng.uniform(0, 1, (n, m)).astype(np.float32)
+    w = f * np.maximum(v, np.float32(1e-3))
+    u = rng.uniform(0, 1, n).astype(np.float32)
+    idx, pmf, W = lighting.wrs_pick(w, u)
+    r = lighting.pick_reservoir(w, f, idx, W)
+    ok = idx >= 0
+    assert np.all(r["M"][ok] == 1) and np.all(r["y"][ok] == idx[ok])
+    assert np.allclose(r["W"][ok] * pmf[ok], 1.0, rtol=3e-7)
+    fy = f[ok, idx[ok]]
+    assert np.allclose(r["w_sum"][ok] / fy, r["W"][ok], rtol=2e-7)
+    lights, pos, nrm, off, mem, vis = _point_scene(5000)
+    out = clustered.sample(vis, pos, nrm, lights, off, mem, seed=1, frame=2, n_cand=8, dtype=np.float32)
+    ok = out["idx"] >= 0
+    fx = lighting.unshadowed_weight(pos[:1], nrm[:1], lights)[0][out["idx"][ok]].astype(np.float32)
+    assert np.allclose(out["w_sum"][ok] / (8 * fx), out["W"][ok], rtol=5e-7)
