@@ -468,22 +468,34 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
 
 // Sum of the blocks' partial weight gradients: slice y of the grid sums
 // blocks [y*G/S, (y+1)*G/S) and adds its sum to g_w (the weight gradient's
-// summation order across slices is not fixed).  The loss is summed once.
+// summation order across slices is not fixed).  The last block column sums
+// the loss once (slice 0 only): a strided pass per thread, then a fixed-order
+// tree in LDS.
 __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ ws_w,
                                                              const float* __restrict__ ws_loss, int nblocks,
                                                              int64_t n_w, float* __restrict__ g_w,
                                                              float* __restrict__ loss_out, float loss_norm) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int S = gridDim.y, y = blockIdx.y;
+    if (blockIdx.x == gridDim.x - 1) {
+        if (y != 0 || !loss_out) return;
+        __shared__ float red[256];
+        float s = 0.0f;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += ws_loss[b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *loss_out = red[0] * loss_norm;
+        return;
+    }
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int b0 = (int)((int64_t)nblocks * y / S), b1 = (int)((int64_t)nblocks * (y + 1) / S);
     if (j < n_w) {
         float s = 0.0f;
         for (int b = b0; b < b1; ++b) s += ws_w[(int64_t)b * n_w + j];
         unsafeAtomicAdd(g_w + j, s);
-    } else if (j == n_w && y == 0 && loss_out) {
-        float s = 0.0f;
-        for (int b = 0; b < nblocks; ++b) s += ws_loss[b];
-        *loss_out = s * loss_norm;
     }
 }
 
@@ -655,9 +667,8 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         err = launch_route_accumulate(gh, a.route, g_table, batch * gh.n_levels * 4, G, st);
         if (err != hipSuccess) return err;
     }
-    const int64_t nthreads = a.n_w + 1;
     const int slices = std::min(G, 16);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((nthreads + 255) / 256), slices), dim3(256), 0, st,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((a.n_w + 255) / 256 + 1), slices), dim3(256), 0, st,
                        a.ws_w, a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
     return hipGetLastError();
 }
