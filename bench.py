@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="train_1080p")
     ap.add_argument("--dtype", default=None, help="override the MLP dtype (f32, f16, bf16)")
+    ap.add_argument("--order", default="morton", choices=["morton", "rows", "shuffled"],
+                    help="pixel order of the G-buffer (morton: tiled; shuffled: the worst case for the gathers)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=655360, help="pixels of the oracle's timed sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=256,
@@ -291,7 +293,7 @@ def main():
         args.workload = "loop_60f"
     wl = get_workload(args.workload, **over)
     dev = torch.device("cuda:0")
-    scene = box_scene(wl.scene_seed, wl.width, wl.height, wl.n_boxes, wl.n_lights, wl.n_spheres)
+    scene = box_scene(wl.scene_seed, wl.width, wl.height, wl.n_boxes, wl.n_lights, wl.n_spheres, order=args.order)
     params = init_params(wl.init_seed, wl.grid, wl.mlp, init=wl.init)
     n_pix = wl.width * wl.height
     B = wl.train_batch
@@ -474,7 +476,8 @@ def main():
         "config": {"workload": wl.name, "pixels": n_pix, "lights": wl.n_lights, "spheres": wl.n_spheres,
                    "train_batch": B, **({"world_batch": wl.world_batch} if wl.world_batch else {}),
                    "grid": f"L{wl.grid.n_levels} F{wl.grid.n_feat} T2^{wl.grid.log2_T}",
-                   "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}"},
+                   "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}",
+                   "pixel_order": args.order},
         "ms_per_frame": ms_per_step,
         "streams": "training half on a second stream beside inference + WRS; stage_ms from a serial pass",
         "timed_launch_ms": {k: round(v, 4) for k, v in timed_ms.items()},

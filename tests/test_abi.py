@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2506_05930_amd import _lib
@@ -194,3 +195,17 @@ def test_python_binding_rejects_cpu_tensors():
     grid = api.make_grid(8, 2, 14, 16, 1.5)
     with pytest.raises(ValueError):
         api.nvc_encode(grid, torch.zeros(8, 1 << 14, 2), torch.zeros(4, 3), torch.zeros(4, 16))
+
+
+def test_scene_pixel_orders_are_permutations_of_one_gbuffer():
+    """The G-buffer orders (tiled Morton, row-major, shuffled) hold the same pixels: each is a permutation of
+    the row-major image, `pixel_xy` says where every stored pixel sits, and the positions agree."""
+    from workloads import box_scene
+    sc = {o: box_scene(0, 48, 20, 8, 4, 8, order=o) for o in ("rows", "morton", "shuffled")}
+    ref = sc["rows"]
+    for o, s in sc.items():
+        xy = s["pixel_xy"].astype(np.int64)
+        idx = xy[:, 1] * 48 + xy[:, 0]
+        assert np.array_equal(np.sort(idx), np.arange(48 * 20)), o
+        assert np.array_equal(s["pos"], ref["pos"][idx]) and np.array_equal(s["nrm"], ref["nrm"][idx]), o
+    assert not np.array_equal(sc["shuffled"]["pixel_xy"], sc["morton"]["pixel_xy"])

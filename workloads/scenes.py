@@ -131,7 +131,8 @@ def box_scene(seed: int, width: int, height: int, n_boxes: int, n_lights: int, n
     """Box room G-buffer: pos/nrm float32 [H*W, 3] in scene units.
 
     order='morton' (default) stores the pixels in Z-order of their (x, y) image
-    coordinates; order='rows' keeps row-major order.  `pixel_xy` [H*W, 2] gives
+    coordinates; order='rows' keeps row-major order; order='shuffled' a seeded
+    random permutation (no locality).  `pixel_xy` [H*W, 2] gives
     the image coordinates of every stored pixel.
 
     Draw order: box min corners U[0,9]^3, box extents U(0.3,1.5)^3 (clipped to
@@ -165,6 +166,8 @@ def box_scene(seed: int, width: int, height: int, n_boxes: int, n_lights: int, n
         perm = morton_order(width, height)
     elif order == "rows":
         perm = np.arange(width * height)
+    elif order == "shuffled":              # no locality at all: the worst case for the table gathers
+        perm = np.random.default_rng(seed + 1000).permutation(width * height)
     else:
         raise ValueError(order)
     pos = np.ascontiguousarray(pos[perm])
