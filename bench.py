@@ -54,6 +54,8 @@ def parse():
                     help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
                          "moving) and print its per-frame report")
     ap.add_argument("--loop-eval", type=int, default=65536, help="pixels of the loop's fixed evaluation subset")
+    ap.add_argument("--micro", action="store_true",
+                    help="instead: the memory microbenchmarks (device copy, random 8-byte gathers)")
     ap.add_argument("--mlp", action="store_true",
                     help="instead: time the MLP alone (nvc_mlp_forward) on the frame's encoding and report its "
                          "matrix-core throughput")
@@ -274,12 +276,54 @@ def run_loop(args, wl, cache, scene, tens, dev):
             "per_frame": frames}
 
 
+def run_micro(reps: int = 20):
+    """What the memory system gives on its own: a plain device copy (HBM stream rate) and random
+    8-byte gathers from tables of 64 MiB (the 1080p hash table's size, held by the 256 MiB last-level
+    cache) and 4 GiB (HBM), with torch's own copy and index_select kernels (not this library's)."""
+    import torch
+    dev = torch.device("cuda:0")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
+    out = {"micro": "memory", "reps": reps}
+    n = 1 << 28                                                   # 1 GiB of float32 each way
+    src, dst = torch.empty(n, device=dev), torch.empty(n, device=dev)
+    src.fill_(1.0)
+    t = timed(lambda: dst.copy_(src))
+    out["copy_GBps"] = round(2 * n * 4 / t / 1e9, 1)              # read + write
+    del src, dst
+    n_g = 1 << 26                                                 # 64 Mi gathers of 8 bytes per launch
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    for name, table_mib in (("gather8_64MiB", 64), ("gather8_4GiB", 4096)):
+        entries = table_mib * (1 << 20) // 8
+        table = torch.zeros(entries, dtype=torch.int64, device=dev)
+        idx = torch.randint(0, entries, (n_g,), device=dev, generator=gen)
+        res = torch.empty(n_g, dtype=torch.int64, device=dev)
+        t = timed(lambda: torch.index_select(table, 0, idx, out=res))
+        out[name + "_Gps"] = round(n_g / t / 1e9, 2)               # gathers per second (x 1e9)
+        del table, idx, res
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.micro:
+        print(json.dumps(run_micro()))
+        return
     import numpy as np
     import torch
 
