@@ -310,6 +310,25 @@ def test_train_gradients_match_oracle(wl_name, dtype, tol, batch, loss):
     assert np.all(g_t[ref["g_table"] == 0] == 0)
 
 
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 3e-2)])
+def test_train_gradients_2pow14_samples(dtype, tol):
+    """The 1080p network's gradient pass on 2^14 samples (many samples per table partition and per
+    training block, several persistent iterations per block) against the oracle."""
+    wl = p1080()
+    p = params(wl)
+    cache = make_cache(wl, p, dtype=dtype)
+    n = 1 << 14
+    pos = rand_pos(31, n)
+    y = (np.random.default_rng(32).uniform(size=(n, wl.mlp.n_out)) > 0.4).astype(np.uint8)
+    cache.gradients(t(pos), labels=t(y))
+    ref = training.train_gradients(pos, p["table"], p["weights"], wl.grid.base_res, wl.grid.growth, labels=y)
+    e_w = _rel_l2(cache.g_w.cpu().numpy(), np.concatenate([g.ravel() for g in ref["g_w"]]))
+    e_t = _rel_l2(cache.g_table.cpu().numpy(), ref["g_table"])
+    print(f"2^14 samples {dtype}: relL2 g_w {e_w:.2e} g_table {e_t:.2e}")
+    assert e_w <= tol and e_t <= tol
+    assert abs(cache.loss_buf.item() - ref["loss"]) <= max(tol, 1e-5) * abs(ref["loss"])
+
+
 def test_gradients_accumulate_and_indirection():
     wl = tiny()
     p = params(wl)
