@@ -215,15 +215,37 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
                 for (int j = 0; j < 2 * F; ++j) w[u][j] = 0.0f;
             }
         }
+        // A thread's records are consecutive, and neighbouring samples often
+        // share a corner pair: runs of equal keys are summed in registers
+        // (exact: integer sums) and each run costs one set of LDS adds.
+        uint32_t kc = key[0];
+        long long acc[2 * F];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t lo0 = key[u] & 0xFFFFu, lo1 = key[u] >> 16;
+        for (int j = 0; j < 2 * F; ++j) acc[j] = to_fixed(w[0][j], scale);
+        auto flush = [&]() {
+            const uint32_t lo0 = kc & 0xFFFFu, lo1 = kc >> 16;
 #pragma unroll
             for (int j = 0; j < F; ++j) {
-                atomicAdd(&part[lo0 * F + j], (unsigned long long)to_fixed(w[u][j], scale));
-                atomicAdd(&part[lo1 * F + j], (unsigned long long)to_fixed(w[u][F + j], scale));
+                if (acc[j] != 0) atomicAdd(&part[lo0 * F + j], (unsigned long long)acc[j]);
+                if (acc[F + j] != 0) atomicAdd(&part[lo1 * F + j], (unsigned long long)acc[F + j]);
+            }
+        };
+#pragma unroll
+        for (int u = 1; u < U; ++u) {
+            long long fx[2 * F];
+#pragma unroll
+            for (int j = 0; j < 2 * F; ++j) fx[j] = to_fixed(w[u][j], scale);
+            if (key[u] == kc) {
+#pragma unroll
+                for (int j = 0; j < 2 * F; ++j) acc[j] += fx[j];
+            } else {
+                flush();
+                kc = key[u];
+#pragma unroll
+                for (int j = 0; j < 2 * F; ++j) acc[j] = fx[j];
             }
         }
+        flush();
     }
     __syncthreads();
     // The partition's entries start at a multiple of 2^k (k >= 12), so the
