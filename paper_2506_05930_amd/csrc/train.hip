@@ -667,7 +667,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         err = launch_route_accumulate(gh, a.route, g_table, batch * gh.n_levels * 4, G, st);
         if (err != hipSuccess) return err;
     }
-    const int slices = std::min(G, 16);
+    const int slices = std::min(G, 64);
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((a.n_w + 255) / 256 + 1), slices), dim3(256), 0, st,
                        a.ws_w, a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
     return hipGetLastError();
