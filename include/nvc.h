@@ -307,7 +307,11 @@ int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int6
 /* One training pass (Sec. 3.3-3.4): re-encode and re-run the network on the
  * batch (activations are recomputed, never stored to memory), take the loss
  * gradient at the output, backpropagate through the MLP on the matrix cores,
- * and scatter the encoding gradient into the hash table with FP32 atomics.
+ * and scatter the encoding gradient into the hash table: routed to 2^k-entry
+ * partitions of the table and summed there exactly (64-bit fixed point in
+ * LDS), with FP32 atomics only for corner pairs that straddle a partition
+ * boundary, partitions summed by several blocks, and grids whose hashed
+ * levels are too fine to partition (then every corner).
  * Sample b uses unit-cube position pos[pix[b]] (pix may be NULL: pos[b]).
  * Mode A (labels != NULL, dvis == NULL): loss over the batch of
  *   NVC_LOSS_BCE: mean over batch*n_out of softplus(z) - y z,
@@ -319,8 +323,9 @@ int64_t nvc_train_workspace_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int6
  * backward and divides the results afterwards (loss scaling; exact in
  * real arithmetic).  0 selects the default (batch*n_out in mode A, 1 in B).
  * Gradients are ADDED to g_table (float32 [L][T][F]) and g_w (float32,
- * master-weight layout); the caller zeroes them (nvc_adam can).  Table
- * atomics make g_table's rounding order nondeterministic.
+ * master-weight layout); the caller zeroes them (nvc_adam can).  Those FP32
+ * atomics, and the weight gradient's sum over slices of the training blocks,
+ * make the last bits of g_table and g_w vary from run to run.
  * workspace: nvc_train_workspace_bytes bytes of device memory. */
 int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                    const void* packed, const float* pos, const int32_t* pix, int64_t batch,
