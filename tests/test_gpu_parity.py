@@ -74,6 +74,7 @@ INFER_CASES = [
     ("frame_1080p", "f32", 2e-5), ("frame_1080p", "f16", 2e-3), ("frame_1080p", "bf16", 3e-2),
     ("sweep_4k", "f32", 2e-5), ("sweep_4k", "f16", 2e-3), ("sweep_4k", "bf16", 3e-2),
     ("paper_1080p", "f32", 2e-5), ("paper_1080p", "f16", 2e-3), ("paper_1080p", "bf16", 3e-2),
+    ("clustered_1080p", "f32", 2e-5), ("clustered_1080p", "f16", 2e-3), ("clustered_1080p", "bf16", 3e-2),
 ]
 
 
@@ -284,7 +285,8 @@ GRAD_CASES = [("tiny", "f32", 1e-4, 1000), ("tiny", "f16", 3e-2, 1000), ("frame_
               ("frame_1080p", "f16", 3e-2, 2085), ("frame_1080p", "bf16", 1e-1, 2085),
               ("sweep_4k", "f32", 1e-4, 700), ("sweep_4k", "f16", 3e-2, 700), ("sweep_4k", "bf16", 1e-1, 700),
               ("paper_1080p", "f32", 1e-4, 1500), ("paper_1080p", "f16", 3e-2, 1500),
-              ("paper_1080p", "bf16", 1e-1, 1500)]
+              ("paper_1080p", "bf16", 1e-1, 1500), ("clustered_1080p", "f32", 1e-4, 1700),
+              ("clustered_1080p", "f16", 3e-2, 1700)]
 
 
 @pytest.mark.parametrize("wl_name,dtype,tol,batch", GRAD_CASES)
