@@ -209,3 +209,15 @@ def test_scene_pixel_orders_are_permutations_of_one_gbuffer():
         assert np.array_equal(np.sort(idx), np.arange(48 * 20)), o
         assert np.array_equal(s["pos"], ref["pos"][idx]) and np.array_equal(s["nrm"], ref["nrm"][idx]), o
     assert not np.array_equal(sc["shuffled"]["pixel_xy"], sc["morton"]["pixel_xy"])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus N > 1 exits with a message (before touching any GPU)."""
+    import json
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
