@@ -225,18 +225,13 @@ def run_loop(args, wl, cache, scene, tens, dev):
 
     from paper_2506_05930_amd import api
     from paper_2506_05930_amd.cache import FrameGraph
-    from workloads import moving_light_table
+    from workloads import LightAnimation, moving_light_table
 
     pos_unit, pos, nrm, lights, spheres = tens
     n_frames = args.loop
     table = torch.as_tensor(moving_light_table(scene["lights"], wl.frames or 60)).to(dev)
-    fg = None
-
-    def pre(stream):
-        idx = fg.ctr[0:1].long() % table.shape[0]
-        lights[0:1].copy_(table.index_select(0, idx))
-
-    fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch, pre=pre)
+    fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch)
+    fg.pre = LightAnimation(table, lights, fg.ctr)
     fg.capture()
     n_pix = pos_unit.shape[0]
     sub = torch.as_tensor(np.random.default_rng(3).choice(n_pix, size=min(args.loop_eval, n_pix), replace=False)

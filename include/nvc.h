@@ -161,6 +161,28 @@ typedef struct nvc_counters {
 /* ctr->frame += 1 and ctr->step += 1, enqueued on `stream`. */
 int nvc_counters_advance(nvc_counters* ctr, void* stream);
 
+/* Recording a frame once and replaying it (Sec. 4: the cache runs every
+ * frame; a frame's launches are the same each time, and the device counters
+ * above make each replay the next frame).  These wrap HIP stream capture.
+ * nvc_graph_begin starts capturing `stream` (a created stream, not NULL:
+ * the legacy default stream cannot be captured), in thread-local mode: this
+ * thread may then make no call that would allocate or synchronise.  Every
+ * entry point of this library may be captured.  Work may fork to other
+ * streams through events recorded on the capturing stream, and every such
+ * stream must be joined back (its last work recorded in an event the
+ * capturing stream waits on) before nvc_graph_end, or capture fails.
+ * nvc_graph_end ends the capture and instantiates it: *exec receives an
+ * executable graph owned by the caller (NULL and NVC_ERR_HIP if capture or
+ * instantiation failed; the stream is no longer capturing either way).
+ * nvc_graph_launch enqueues one replay on `stream` (not NULL); replays on
+ * one stream run in order.  nvc_graph_destroy releases the executable (not
+ * while a replay may still run: synchronise first).  The buffers the
+ * recorded calls received must stay allocated while the graph is used. */
+int nvc_graph_begin(void* stream);
+int nvc_graph_end(void* stream, void** exec);
+int nvc_graph_launch(void* exec, void* stream);
+int nvc_graph_destroy(void* exec);
+
 /* Light selection by weighted reservoir sampling (Sec. 1, Sec. 3.1) and
  * neural direct illumination (Sec. 3.2).
  * vis: [n][m] in vis_dtype; pos: float32 [n][3] in scene units; nrm:
@@ -207,6 +229,23 @@ int64_t nvc_select_pixels_workspace_bytes(int64_t n_pix);
  * 1 <= n_pix < 2^31, 0 <= batch < 2^31. */
 int nvc_select_pixels(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
                       int32_t* pix, void* workspace, int64_t workspace_bytes, void* stream);
+
+/* nvc_select_pixels without allocation or workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same result as
+ * nvc_select_pixels; the workspace is a static device buffer inside the
+ * library, sized for n_pix <= NVC_SELECT_PIXELS_NOALLOC_MAX_PIX (2^23 pixels:
+ * 64 MiB + 8.5 KiB), which each GPU the library runs on holds until the
+ * process ends.  Larger images: NVC_ERR_SHAPE, nothing enqueued.  The first
+ * call on a device (the current device) looks up the buffer's address there
+ * (no allocation, but it may load the library's code on that device: make it
+ * outside stream capture).  Every call on a GPU shares that GPU's buffer and
+ * keeps nothing from the previous call: calls that overlap on one GPU (e.g.
+ * on two streams without an ordering between them) race and must be
+ * serialised by the caller.  ctr as in nvc_select_pixels. */
+#define NVC_SELECT_PIXELS_NOALLOC_MAX_PIX (1 << 23)
+int nvc_select_pixels_noalloc(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
+                              int32_t* pix, void* stream);
 
 /* World-space training points (Sec. 3.4: training examples at random scene
  * positions, which prepare the cache for views it has not seen yet; the

@@ -22,6 +22,7 @@ NVC_ERR_WORKSPACE = -6
 NVC_F32, NVC_F16, NVC_BF16 = 0, 1, 2
 NVC_ACT_RELU, NVC_ACT_LEAKY = 0, 1
 NVC_LOSS_BCE, NVC_LOSS_L2 = 0, 1
+NVC_SELECT_PIXELS_NOALLOC_MAX_PIX = 1 << 23
 
 EXPORTS = [
     "nvc_version", "nvc_status_string", "nvc_grid_levels", "nvc_mlp_param_count", "nvc_mlp_packed_bytes",
@@ -29,6 +30,7 @@ EXPORTS = [
     "nvc_select_pixels", "nvc_shadow_labels",
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
     "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered", "nvc_world_samples",
+    "nvc_graph_begin", "nvc_graph_end", "nvc_graph_launch", "nvc_graph_destroy", "nvc_select_pixels_noalloc",
 ]
 
 
@@ -65,6 +67,7 @@ _SIGS = {
     "nvc_select_pixels_workspace_bytes": (c_int64, [c_int64]),
     "nvc_select_pixels": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_int64, c_void_p, c_void_p, c_int64,
                                     c_void_p]),
+    "nvc_select_pixels_noalloc": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_int64, c_void_p, c_void_p]),
     "nvc_shadow_labels": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32, c_void_p,
                                     c_void_p]),
     "nvc_train_workspace_bytes": (c_int64, [POINTER(NvcGrid), POINTER(NvcMlp), c_int64]),
@@ -74,6 +77,10 @@ _SIGS = {
     "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_float, c_float,
                            c_int32, c_float, c_float, c_float, c_int32, c_void_p]),
     "nvc_counters_advance": (c_int32, [c_void_p, c_void_p]),
+    "nvc_graph_begin": (c_int32, [c_void_p]),
+    "nvc_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
+    "nvc_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "nvc_graph_destroy": (c_int32, [c_void_p]),
     "nvc_world_samples": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_void_p, c_float, c_void_p, c_void_p,
                                     c_void_p]),
     "nvc_cluster_lights": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),

@@ -43,10 +43,91 @@ def make_mlp(n_in, width, n_hidden, n_out, act="relu", leaky_slope=0.01, dtype="
 
 def _stream(stream) -> int:
     if stream is None:
-        return torch.cuda.current_stream().cuda_stream
-    if isinstance(stream, torch.cuda.Stream):
-        return stream.cuda_stream
-    return int(stream)
+        h = torch.cuda.current_stream().cuda_stream
+    elif isinstance(stream, torch.cuda.Stream):
+        h = stream.cuda_stream
+    else:
+        h = int(stream)
+    if _ledger is not None:
+        _ledger.use(h)
+    return h
+
+
+class CaptureLedger:
+    """Which streams a recording has forked from the capturing stream, and whether each was joined back
+    after its last library call.
+
+    While a ledger is active (`recording(ledger)`), every entry point of this module notes the stream it
+    enqueues on; `fork` / `join` (below) note the event edges between streams.  HIP ends a capture only when
+    every stream that received captured work has been joined back to the capturing stream; `check` raises
+    before that point instead, naming the streams that were not joined or never forked.
+    """
+
+    def __init__(self, origin: int):
+        self.origin = int(origin)
+        self.forked: set[int] = set()
+        self.pending: set[int] = set()      # forked streams with library calls after their last join
+        self.stray: set[int] = set()        # streams used without a fork from the capture
+
+    def use(self, h: int) -> None:
+        h = int(h)
+        if h == self.origin:
+            return
+        if h in self.forked:
+            self.pending.add(h)
+        else:
+            self.stray.add(h)
+
+    def fork(self, h: int) -> None:
+        self.forked.add(int(h))
+
+    def join(self, h: int) -> None:
+        self.pending.discard(int(h))
+
+    def check(self) -> None:
+        if self.pending or self.stray:
+            raise RuntimeError("graph recording: streams with work not joined back to the capturing stream: "
+                               f"{sorted(self.pending)}; streams used without a fork from it: {sorted(self.stray)}")
+
+
+_ledger: CaptureLedger | None = None
+
+
+class recording:
+    """Context manager making `ledger` the active capture ledger."""
+
+    def __init__(self, ledger: CaptureLedger):
+        self.ledger = ledger
+
+    def __enter__(self):
+        global _ledger
+        if _ledger is not None:
+            raise RuntimeError("a graph recording is already active")
+        _ledger = self.ledger
+        return self.ledger
+
+    def __exit__(self, *exc):
+        global _ledger
+        _ledger = None
+        return False
+
+
+def _handle(stream) -> int:
+    return stream.cuda_stream if isinstance(stream, torch.cuda.Stream) else int(stream)
+
+
+def fork(side: torch.cuda.Stream, main: torch.cuda.Stream) -> None:
+    """side waits for the work enqueued on main so far (an event edge; also inside a recording)."""
+    side.wait_stream(main)
+    if _ledger is not None and _handle(main) in (_ledger.origin, *_ledger.forked):
+        _ledger.fork(_handle(side))
+
+
+def join(main: torch.cuda.Stream, side: torch.cuda.Stream) -> None:
+    """main waits for the work enqueued on side so far."""
+    main.wait_stream(side)
+    if _ledger is not None:
+        _ledger.join(_handle(side))
 
 
 def _ptr(t, name, dtype=None, shape=None, optional=False):
@@ -135,6 +216,26 @@ def nvc_counters_advance(ctr: torch.Tensor, stream=None) -> None:
     _lib.check("nvc_counters_advance", _lib.load().nvc_counters_advance(_counters(ctr), _stream(stream)))
 
 
+def nvc_graph_begin(stream) -> None:
+    """Start recording `stream` (a created stream, not the default one) into a HIP graph."""
+    _lib.check("nvc_graph_begin", _lib.load().nvc_graph_begin(_stream(stream)))
+
+
+def nvc_graph_end(stream) -> int:
+    """End the recording of `stream`; returns the executable graph's handle (owned by the caller)."""
+    ex = ctypes.c_void_p()
+    _lib.check("nvc_graph_end", _lib.load().nvc_graph_end(_stream(stream), ctypes.byref(ex)))
+    return int(ex.value)
+
+
+def nvc_graph_launch(exec_handle: int, stream=None) -> None:
+    _lib.check("nvc_graph_launch", _lib.load().nvc_graph_launch(ctypes.c_void_p(exec_handle), _stream(stream)))
+
+
+def nvc_graph_destroy(exec_handle: int) -> None:
+    _lib.check("nvc_graph_destroy", _lib.load().nvc_graph_destroy(ctypes.c_void_p(exec_handle)))
+
+
 def nvc_mlp_forward(mlp: NvcMlp, packed: torch.Tensor, enc: torch.Tensor, vis: torch.Tensor, stream=None) -> None:
     n = enc.shape[0]
     pk = _ptr(packed, "packed")
@@ -179,6 +280,14 @@ def nvc_select_pixels(seed: int, frame: int, n_pix: int, pix: torch.Tensor, work
                                                                   pix.numel(), pp, pw,
                                                                   workspace.numel() * workspace.element_size(),
                                                                   _stream(stream)))
+
+
+def nvc_select_pixels_noalloc(seed: int, frame: int, n_pix: int, pix: torch.Tensor, stream=None, ctr=None) -> None:
+    """nvc_select_pixels with the library's static workspace (no allocation; n_pix <= 2^23)."""
+    pp = _ptr(pix, "pix", torch.int32)
+    _lib.check("nvc_select_pixels_noalloc", _lib.load().nvc_select_pixels_noalloc(
+        int(seed) & (2 ** 64 - 1), int(frame) & 0xFFFFFFFF, _counters(ctr), int(n_pix), pix.numel(), pp,
+        _stream(stream)))
 
 
 def nvc_shadow_labels(pos: torch.Tensor, pix, lights: torch.Tensor, spheres: torch.Tensor, labels: torch.Tensor,

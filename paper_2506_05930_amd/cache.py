@@ -210,13 +210,13 @@ class NVCache:
                                             stream=stream, ctr=ctr)
             return bufs
         main = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.current_stream()
-        side.wait_stream(main)
+        api.fork(side, main)
         bufs["train"] = self.train_gradients(pos_unit, pos_scene, lights, spheres, frame, batch, bufs.get("train"),
                                              stream=side, ctr=ctr)
         self.infer(pos_unit, bufs["vis"], stream=main)
         bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=main,
                                      ctr=ctr)
-        main.wait_stream(side)
+        api.join(main, side)
         self.adam(main, ctr=ctr)
         return bufs
 
@@ -245,14 +245,21 @@ class FrameGraph:
     device-counter increment; the frame number and the Adam step are read from the counters
     `ctr` (int32 [2]) when the kernels run, so every replay is the next
     frame.  `pre(stream)`, if given, is recorded first (e.g. scene animation
-    driven by `ctr`).  Every buffer is allocated before capture; the library
-    calls allocate nothing, issue no memset and never synchronise.
+    driven by `ctr`); it must not allocate device memory.  Every buffer is
+    allocated before the recording; the library calls allocate nothing, issue
+    no memset and never synchronise.  Recording and replay go through the
+    library's nvc_graph_begin / nvc_graph_end / nvc_graph_launch.  Before the
+    recording ends, the capture ledger checks that the training stream was
+    joined back after its last call, and the torch allocator's counters that
+    nothing was allocated while recording (such memory could be handed to
+    another tensor later while the graph still writes it): either raises.
     """
 
     def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, pre=None,
                  frame0: int = 0, concurrent: bool = True):
         self.cache = cache
         self.side = torch.cuda.Stream(device=cache.device) if concurrent else None
+        self.stream = torch.cuda.Stream(device=cache.device)      # the recorded (and replaying) stream
         self.args = (pos_unit, pos_scene, nrm, lights, spheres)
         self.batch = int(batch)
         self.pre = pre
@@ -268,7 +275,7 @@ class FrameGraph:
                                "labels": torch.empty((self.batch, cache.mlp.n_out), dtype=torch.uint8, device=dev)}}
         cache._ensure_workspace(self.batch)
         cache.pixel_workspace(n)
-        self.graph = None
+        self.exec = None
 
     def _body(self, stream):
         if self.pre is not None:
@@ -281,55 +288,101 @@ class FrameGraph:
         self._body(torch.cuda.current_stream())
         self.cache.step += 1
 
+    @staticmethod
+    def _allocations() -> int:
+        return int(torch.cuda.memory_stats().get("allocation.all.allocated", 0))
+
     def capture(self):
         torch.cuda.synchronize()
         saved = self.ctr.clone()
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):        # warm-up of the recorded torch work, then restore the state
+        st = self.stream
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):         # warm-up of the recorded torch work, then restore the state
             if self.pre is not None:
-                self.pre(side)
-        torch.cuda.current_stream().wait_stream(side)
+                self.pre(st)
         torch.cuda.synchronize()
         self.ctr.copy_(saved)
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            self._body(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ledger = api.CaptureLedger(st.cuda_stream)
+        n_alloc = self._allocations()
+        api.nvc_graph_begin(st)
+        problem = None
+        try:
+            with torch.cuda.stream(st), api.recording(ledger):
+                self._body(st)
+                try:
+                    ledger.check()
+                except RuntimeError as e:
+                    problem = e
+                    if self.side is not None:          # join so that the capture can still be ended cleanly
+                        api.join(st, self.side)
+        except BaseException:
+            try:                                       # end the capture, drop what it recorded
+                api.nvc_graph_destroy(api.nvc_graph_end(st))
+            except Exception:
+                pass
+            raise
+        ex = api.nvc_graph_end(st)
+        if problem is None and self._allocations() != n_alloc:
+            problem = RuntimeError("graph recording: device memory was allocated while recording")
+        if problem is not None:
+            api.nvc_graph_destroy(ex)
+            raise problem
+        self.exec = ex
         torch.cuda.synchronize()
         return self
 
     def replay(self):
-        if self.graph is None:
+        if self.exec is None:
             self.capture()
-        self.graph.replay()
+        st = self.stream
+        st.wait_stream(torch.cuda.current_stream())
+        api.nvc_graph_launch(self.exec, st)
+        torch.cuda.current_stream().wait_stream(st)
         self.cache.step += 1
+
+    def close(self):
+        if self.exec is not None:
+            torch.cuda.synchronize()
+            api.nvc_graph_destroy(self.exec)
+            self.exec = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class NVCFunction(torch.autograd.Function):
     """vis = sigmoid(MLP(encode(pos))) with gradients for the table and the FP32 master weights.
 
-    forward packs `w` and runs nvc_infer (FP32 output); backward runs
-    nvc_train_step with the upstream gradient, recomputing the activations.
+    forward packs `w` into a packed copy of its own (the cache's `packed`,
+    which inference uses, is left alone) and runs nvc_infer (FP32 output);
+    backward runs nvc_train_step with the upstream gradient on that same
+    packed copy and the saved table, recomputing the activations, so other
+    forwards, repacks or Adam steps between the two do not change the result.
     """
 
     @staticmethod
     def forward(ctx, pos_unit, table, w, cache: NVCache, grad_scale: float = 0.0):
-        api.nvc_pack_mlp(cache.mlp, w.detach().contiguous(), cache.packed)
+        packed = torch.empty(api.nvc_mlp_packed_bytes(cache.mlp), dtype=torch.uint8, device=pos_unit.device)
+        api.nvc_pack_mlp(cache.mlp, w.detach().contiguous(), packed)
         vis = torch.empty((pos_unit.shape[0], cache.mlp.n_out), dtype=torch.float32, device=pos_unit.device)
-        api.nvc_infer(cache.grid, cache.mlp, table.detach().contiguous(), cache.packed, pos_unit, vis)
-        ctx.save_for_backward(pos_unit, table, w)
+        api.nvc_infer(cache.grid, cache.mlp, table.detach().contiguous(), packed, pos_unit, vis)
+        ctx.save_for_backward(pos_unit, table, w, packed)
         ctx.cache = cache
         ctx.grad_scale = grad_scale
         return vis
 
     @staticmethod
     def backward(ctx, dvis):
-        pos_unit, table, w = ctx.saved_tensors
+        pos_unit, table, w, packed = ctx.saved_tensors
         cache = ctx.cache
         g_table = torch.zeros_like(table)
         g_w = torch.zeros_like(w)
         cache._ensure_workspace(pos_unit.shape[0])
-        api.nvc_train_step(cache.grid, cache.mlp, table.detach().contiguous(), cache.packed, pos_unit, None,
+        api.nvc_train_step(cache.grid, cache.mlp, table.detach().contiguous(), packed, pos_unit, None,
                            pos_unit.shape[0], None, dvis.contiguous().float(), cache.loss, ctx.grad_scale,
                            g_table, g_w, None, cache.workspace)
         return None, g_table, g_w, None, None

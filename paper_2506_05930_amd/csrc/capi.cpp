@@ -194,6 +194,16 @@ int nvc_select_pixels(uint64_t seed, uint32_t frame, const nvc_counters* ctr, in
                                            (hipStream_t)stream));
 }
 
+int nvc_select_pixels_noalloc(uint64_t seed, uint32_t frame, const nvc_counters* ctr, int64_t n_pix, int64_t batch,
+                              int32_t* pix, void* stream) {
+    if (n_pix < 1 || n_pix > select_pixels_noalloc_max_pixels() || batch < 0 || batch >= ((int64_t)1 << 31))
+        return NVC_ERR_SHAPE;
+    if (batch == 0) return NVC_OK;
+    if (!pix) return NVC_ERR_NULL;
+    return hip_status(launch_select_pixels_noalloc(seed, frame, ctr ? &ctr->frame : nullptr, n_pix, batch, pix,
+                                                   (hipStream_t)stream));
+}
+
 int nvc_shadow_labels(const float* pos, const int32_t* pix, int64_t n, const float* lights, int32_t m,
                       const float* spheres, int32_t n_spheres, uint8_t* labels, void* stream) {
     if (n < 0 || m < 1 || m > 128 || n_spheres < 0 || n_spheres > 4096) return NVC_ERR_SHAPE;
@@ -302,6 +312,38 @@ int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step
 int nvc_counters_advance(nvc_counters* ctr, void* stream) {
     if (!ctr) return NVC_ERR_NULL;
     return hip_status(launch_counters_advance(&ctr->frame, &ctr->step, (hipStream_t)stream));
+}
+
+int nvc_graph_begin(void* stream) {
+    if (!stream) return NVC_ERR_NULL;       // the legacy default stream cannot be captured
+    return hip_status(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+}
+
+int nvc_graph_end(void* stream, void** exec) {
+    if (!stream || !exec) return NVC_ERR_NULL;
+    *exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return NVC_ERR_HIP;
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);           // the executable keeps what it needs
+    if (e != hipSuccess) return NVC_ERR_HIP;
+    *exec = (void*)ge;
+    return NVC_OK;
+}
+
+int nvc_graph_launch(void* exec, void* stream) {
+    if (!exec || !stream) return NVC_ERR_NULL;
+    return hip_status(hipGraphLaunch((hipGraphExec_t)exec, (hipStream_t)stream));
+}
+
+int nvc_graph_destroy(void* exec) {
+    if (!exec) return NVC_ERR_NULL;
+    return hip_status(hipGraphExecDestroy((hipGraphExec_t)exec));
 }
 
 }  // extern "C"

@@ -83,6 +83,9 @@ hipError_t launch_wrs(const void* vis, int vis_dtype, int64_t n, int m, const fl
 int64_t select_pixels_workspace_bytes(int64_t n_pix);
 hipError_t launch_select_pixels(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
                                 int64_t batch, int32_t* pix, void* workspace, hipStream_t st);
+int64_t select_pixels_noalloc_max_pixels();
+hipError_t launch_select_pixels_noalloc(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n_pix,
+                                        int64_t batch, int32_t* pix, hipStream_t st);
 size_t labels_smem_bytes(int m, int n_spheres);
 hipError_t launch_world_samples(uint64_t seed, uint32_t frame, const uint32_t* frame_dev, int64_t n, const float* box,
                                 float extent, float* pos_scene, float* pos_unit, hipStream_t st);

@@ -525,12 +525,16 @@ static int train_grid(const GridHost& gh, const NetShape& s, int64_t batch, size
 
 static size_t route_cursor_bytes(const RoutePlan& rp) { return rp.ok ? (size_t)rp.nb * 4 : 0; }
 
-// The routed scatter for this shape, if its cursors fit the LDS beside the activations.
-static RoutePlan train_route_plan(const GridHost& g, const NetShape& s) {
+// The routed scatter for this shape and batch, if its cursors fit the LDS
+// beside the activations and its record numbers fit the 32-bit offsets,
+// bucket bases and cursors (batch * n_levels * 4 records < 2^32).  Otherwise
+// every corner goes through direct FP32 atomics.
+static RoutePlan train_route_plan(const GridHost& g, const NetShape& s, int64_t batch) {
     RoutePlan rp = make_route_plan(g);
     size_t smem = 0;
     dispatch_config(g.n_feat, s, [&]<class C>() { smem = TrainShape<C>::SMEM; });
     if (rp.ok && smem + route_cursor_bytes(rp) > 160 * 1024) rp.ok = false;
+    if (rp.ok && batch * (int64_t)g.n_levels * 4 >= ((int64_t)1 << 32)) rp.ok = false;
     return rp;
 }
 
@@ -586,7 +590,7 @@ static int64_t n_weights(const NetShape& s) {
 }
 
 int64_t train_workspace_bytes(const GridHost& g, const NetShape& s, int64_t batch) {
-    const RoutePlan rp = train_route_plan(g, s);
+    const RoutePlan rp = train_route_plan(g, s, batch);
     return ws_layout(g, n_weights(s), batch, train_grid(g, s, batch, route_cursor_bytes(rp)), rp).total;
 }
 
@@ -625,7 +629,7 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
         a.final_mul = (float)(1.0 / gs);
     }
     a.g_table = g_table;
-    const RoutePlan rp = train_route_plan(gh, s);
+    const RoutePlan rp = train_route_plan(gh, s, batch);
     const size_t cursor_bytes = route_cursor_bytes(rp);
     const int G = train_grid(gh, s, batch, cursor_bytes);
     const WsLayout wl = ws_layout(gh, a.n_w, batch, G, rp);

@@ -188,6 +188,20 @@ def test_train_step_validation(lib):
         _lib.NVC_ERR_UNSUPPORTED
 
 
+def test_routed_scatter_is_limited_to_32_bit_record_numbers(lib):
+    """The routed table scatter numbers its batch * n_levels * 4 records with 32-bit offsets; a batch that
+    would reach 2^32 records trains through direct atomics instead, whose workspace holds no records."""
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())           # 16 levels: the limit is 2^26 samples
+    routed = lib.nvc_train_workspace_bytes(gg, mm, (1 << 26) - 1)
+    direct = lib.nvc_train_workspace_bytes(gg, mm, 1 << 26)
+    assert routed > ((1 << 26) - 1) * 16 * 4 * 20           # 20-byte records of every corner x-pair
+    assert 0 < direct < routed // 1000
+    # a batch the entry point refuses outright
+    P = ctypes.c_void_p(16)
+    assert lib.nvc_train_step(gg, mm, P, P, P, None, 1 << 31, P, None, 0, 0.0, P, P, None, P, direct, None) == \
+        _lib.NVC_ERR_SHAPE
+
+
 def test_python_binding_rejects_cpu_tensors():
     import torch
 
@@ -221,3 +235,63 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     out = json.loads(r.stdout.strip().splitlines()[-1])
     assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+def test_graph_entry_points_validate_before_calling_hip(lib):
+    P = ctypes.c_void_p(16)
+    ex = ctypes.c_void_p()
+    assert lib.nvc_graph_begin(None) == _lib.NVC_ERR_NULL          # the legacy default stream cannot be captured
+    assert lib.nvc_graph_end(None, ctypes.byref(ex)) == _lib.NVC_ERR_NULL
+    assert lib.nvc_graph_end(P, None) == _lib.NVC_ERR_NULL
+    assert lib.nvc_graph_launch(None, P) == _lib.NVC_ERR_NULL
+    assert lib.nvc_graph_launch(P, None) == _lib.NVC_ERR_NULL
+    assert lib.nvc_graph_destroy(None) == _lib.NVC_ERR_NULL
+
+
+def test_capture_ledger_names_streams_not_joined_back():
+    """The host-side guard of a graph recording: every stream that received library calls must have been
+    forked from the capturing stream and joined back to it after its last call (HIP refuses to end a
+    capture otherwise).  Streams are plain handles here; the binding notes each call's stream."""
+    from paper_2506_05930_amd import api
+    origin, side, other = 1001, 1002, 1003
+    ok = api.CaptureLedger(origin)
+    with api.recording(ok):
+        api._stream(origin)
+        ok.fork(side)
+        api._stream(side)
+        api._stream(origin)
+        ok.join(side)
+    ok.check()
+    # work on the side stream after its join is not joined
+    late = api.CaptureLedger(origin)
+    late.fork(side)
+    late.use(side)
+    late.join(side)
+    with api.recording(late):
+        api._stream(side)
+    with pytest.raises(RuntimeError, match=str(side)):
+        late.check()
+    # a stream that was never forked from the capture
+    stray = api.CaptureLedger(origin)
+    with api.recording(stray):
+        api._stream(other)
+    with pytest.raises(RuntimeError, match=str(other)):
+        stray.check()
+    # recordings do not nest, and the ledger is released afterwards
+    with api.recording(api.CaptureLedger(origin)):
+        with pytest.raises(RuntimeError):
+            with api.recording(api.CaptureLedger(origin)):
+                pass
+    assert api._ledger is None
+
+
+def test_noalloc_pixel_selection_validates_before_launching(lib):
+    P = ctypes.c_void_p(16)
+    big = _lib.NVC_SELECT_PIXELS_NOALLOC_MAX_PIX
+    assert lib.nvc_select_pixels_noalloc(0, 0, None, big + 1, 10, P, None) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels_noalloc(0, 0, None, 0, 10, P, None) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels_noalloc(0, 0, None, 100, -1, P, None) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_select_pixels_noalloc(0, 0, None, 100, 10, None, None) == _lib.NVC_ERR_NULL
+    assert lib.nvc_select_pixels_noalloc(0, 0, None, 100, 0, None, None) == 0      # empty batch: no-op
+    hdr = open(HEADER).read()
+    assert f"#define NVC_SELECT_PIXELS_NOALLOC_MAX_PIX (1 << {big.bit_length() - 1})" in hdr

@@ -13,7 +13,7 @@ import torch
 from paper_2506_05930_amd import api
 from paper_2506_05930_amd.cache import FrameGraph
 from tests.gpu_common import make_cache, p1080, params
-from workloads import box_scene, moving_light_table
+from workloads import LightAnimation, box_scene, moving_light_table
 
 pytestmark = pytest.mark.gpu
 
@@ -72,13 +72,8 @@ def test_frame_graph_replays_match_eager(scene):
         pos_unit, pos, nrm = t(scene["pos_unit"]), t(scene["pos"]), t(scene["nrm"])
         lights, spheres = t(base), t(scene["spheres"])
         tab = t(table_np)
-        fg = None
-
-        def pre(stream):
-            idx = fg.ctr[0:1].long() % tab.shape[0]
-            lights[0:1].copy_(tab.index_select(0, idx))
-
-        fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, batch, pre=pre)
+        fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, batch)
+        fg.pre = LightAnimation(tab, lights, fg.ctr)
         return cache, fg, lights
 
     ce, fe, le = setup()

@@ -14,10 +14,11 @@ from .scenes import (
     pos_to_unit,
     moving_light,
     moving_light_table,
+    LightAnimation,
 )
 
 __all__ = [
     "GridCfg", "MlpCfg", "Workload", "WORKLOADS", "get_workload",
     "unit_cube_scene", "box_scene", "init_params", "pos_to_unit", "moving_light",
-    "moving_light_table",
+    "moving_light_table", "LightAnimation",
 ]

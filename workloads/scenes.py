@@ -221,6 +221,27 @@ def moving_light_table(lights: np.ndarray, n_frames: int = 60, radius: float = 3
     return np.stack([moving_light(lights, f, n_frames, radius, center_xz)[0] for f in range(n_frames)]).astype(np.float32)
 
 
+class LightAnimation:
+    """Per-frame scene update for a recorded frame: light 0 <- row (frame mod n_frames) of a table of
+    its positions, the frame read from device counters at run time.  Every buffer is allocated here, so a
+    call allocates nothing (it may be recorded into a graph).  table: device float32 [n_frames][4];
+    lights: device float32 [m][4]; ctr: device int32 [2] (frame, step)."""
+
+    def __init__(self, table, lights, ctr):
+        import torch
+        self.table, self.lights, self.ctr = table, lights, ctr
+        self.idx = torch.zeros(1, dtype=torch.int64, device=table.device)
+        self.row = torch.empty((1, 4), dtype=torch.float32, device=table.device)
+        self.n = int(table.shape[0])
+
+    def __call__(self, stream=None):
+        import torch
+        self.idx.copy_(self.ctr[0:1])
+        torch.remainder(self.idx, self.n, out=self.idx)
+        torch.index_select(self.table, 0, self.idx, out=self.row)
+        self.lights[0:1].copy_(self.row)
+
+
 def flatten_weights(weights) -> np.ndarray:
     """Concatenate per-layer [out][in] FP32 matrices into the flat master-weight buffer."""
     return np.concatenate([w.reshape(-1) for w in weights]).astype(np.float32)
