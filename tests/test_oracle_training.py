@@ -260,3 +260,60 @@ def test_world_points_uniform_in_the_box():
     # the first coordinate is the uniform of the first Philox word of counter (i, frame, 6)
     w = philox.philox4x32_10(philox._counter(np.arange(5, dtype=np.uint64), 3, 6), philox._key(2))[0]
     assert np.allclose(p[:5, 0], lo[0] + philox.uniform24(w).astype(np.float64) * 9.0, rtol=1e-6)
+
+
+def test_pipeline_train_step_matches_torch_autograd_and_adam():
+    """The composed training step (Sec. 3.4: pick pixels, label them with shadow rays, backpropagate,
+    one Adam step on every parameter) against an independent route: torch FP64 autograd through the
+    corner gather and torch.optim.Adam on [table, W_1, ...], three steps with the optimiser state
+    carried.  The pixel draws and shadow labels it consumes are pinned on their own (Random123 known
+    answers; analytic and brute-force label cases); this checks how the step wires them together:
+    which positions are trained, which gradient reaches which parameter, and the Adam state."""
+    from oracle import philox, pipeline, shadow
+    from workloads import unit_cube_scene
+    sc = unit_cube_scene(4, 300, 8, 12)
+    rng = np.random.default_rng(8)
+    L, T, F = 4, 1 << 9, 2
+    base, growth = 4, 1.5
+    table = rng.uniform(-0.5, 0.5, size=(L, T, F)).astype(np.float32)
+    weights = [rng.normal(scale=0.5, size=s).astype(np.float32) for s in [(16, 8), (16, 16), (8, 16)]]
+    res = hashgrid.level_resolutions(base, growth, L)
+    tt = torch.from_numpy(table.astype(np.float64)).requires_grad_(True)
+    ws = [torch.from_numpy(w.astype(np.float64)).requires_grad_(True) for w in weights]
+    opt = torch.optim.Adam([tt, *ws], lr=0.02, betas=(0.9, 0.99), eps=1e-8)
+    state, cur_t, cur_w = None, table, weights
+    batch = 200
+    for frame in range(3):
+        out = pipeline.train_step(sc["pos"], sc["pos"], sc["lights"], sc["spheres"], cur_t, cur_w, base, growth,
+                                  seed=5, frame=frame, batch=batch, adam_state=state, lr=0.02)
+        pix = philox.training_pixels(5, frame, batch, sc["pos"].shape[0])
+        assert np.array_equal(out["pix"], pix)
+        y = shadow.labels_fp32(sc["pos"][pix], sc["lights"], sc["spheres"])
+        assert np.array_equal(out["labels"], y) and 0.05 < y.mean() < 0.99
+        p = sc["pos"][pix]
+        opt.zero_grad()
+        feats = []
+        for l in range(L):
+            idx, w = hashgrid.corners(p, res[l], T)
+            feats.append((torch.from_numpy(w)[:, :, None] * tt[l][torch.from_numpy(idx)]).sum(1))
+        h = torch.cat(feats, 1)
+        for k, W in enumerate(ws):
+            h = h @ W.T
+            if k < len(ws) - 1:
+                h = torch.relu(h)
+        lt = torch.nn.functional.binary_cross_entropy_with_logits(h, torch.from_numpy(y.astype(np.float64)))
+        lt.backward()
+        opt.step()
+        assert abs(lt.item() - out["loss"]) <= 1e-13
+        assert np.max(np.abs(tt.detach().numpy() - out["table"])) <= 1e-12
+        for k in range(len(ws)):
+            assert np.max(np.abs(ws[k].detach().numpy() - out["weights"][k])) <= 1e-12
+        assert out["adam"]["t"] == frame + 1
+        # the next step starts from the updated parameters (FP64 carried, as torch does)
+        state, cur_t, cur_w = out["adam"], out["table"], out["weights"]
+    # entries no sample touched moved only by their earlier steps' moments: at step 1 an untouched
+    # entry has g = 0 and stays put
+    first = pipeline.train_step(sc["pos"], sc["pos"], sc["lights"], sc["spheres"], table, weights, base, growth,
+                                seed=5, frame=0, batch=batch, lr=0.02)
+    untouched = first["grads"]["g_table"] == 0
+    assert untouched.any() and np.array_equal(first["table"][untouched], table.astype(np.float64)[untouched])
