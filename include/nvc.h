@@ -389,6 +389,31 @@ int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step
              float lr, float lr_end, int32_t lr_decay_steps, float beta1, float beta2, float eps,
              int32_t zero_grad, void* stream);
 
+/* FP64 forward pass and training loss, for checking gradients by central
+ * finite differences (Sec. 3.3: the cache is trained by backpropagation; a
+ * difference quotient with a step of 1e-3 needs the loss to many more digits
+ * than the FP16 / FP32 paths give).  Not a hot-path call: plain FP64
+ * arithmetic on the vector units, one block per point.
+ * table: double [L][T][F]; w: double, the master-weight layout (per layer
+ * [out][in], input layer first); pos: float32 [n][3] unit cube, clamped as in
+ * nvc_encode.  The cell and fraction of a position are decided in FP32 as in
+ * every other kernel (s = fl32(x N)); trilinear weights, features, network,
+ * sigmoid and loss are FP64; dot products run over their inputs in index
+ * order.  mlp->dtype is ignored.
+ * z: double [n][n_out] logits, or NULL.
+ * masks: uint8 [n][n_hidden][ceil(width/8)], or NULL: bit j%8 of byte j/8 of
+ *   layer k is set iff hidden pre-activation j of layer k is > 0 (the ReLU /
+ *   leaky-ReLU branch taken), so that a caller can tell whether a
+ *   perturbation changed any branch.
+ * labels: uint8 [n][n_out] (0/1), or NULL.  With labels, loss_out (double,
+ *   n + 1 entries) receives each point's loss summed over its outputs in order
+ *   (NVC_LOSS_BCE: softplus(z) - y z; NVC_LOSS_L2: (sigmoid(z) - y)^2) and,
+ *   at [n], their mean over n * n_out, summed over the points in index order.
+ * n in [0, 2^20] (else NVC_ERR_SHAPE); n = 0 is a no-op. */
+int nvc_forward_f64(const nvc_grid* grid, const nvc_mlp* mlp, const double* table, const double* w,
+                    const float* pos, int64_t n, const uint8_t* labels, int32_t loss, double* z,
+                    uint8_t* masks, double* loss_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,7 @@ EXPORTS = [
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
     "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered", "nvc_world_samples",
     "nvc_graph_begin", "nvc_graph_end", "nvc_graph_launch", "nvc_graph_destroy", "nvc_select_pixels_noalloc",
+    "nvc_forward_f64",
 ]
 
 
@@ -81,6 +82,8 @@ _SIGS = {
     "nvc_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "nvc_graph_launch": (c_int32, [c_void_p, c_void_p]),
     "nvc_graph_destroy": (c_int32, [c_void_p]),
+    "nvc_forward_f64": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_int64, c_void_p,
+                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nvc_world_samples": (c_int32, [c_uint64, c_uint32, c_void_p, c_int64, c_void_p, c_float, c_void_p, c_void_p,
                                     c_void_p]),
     "nvc_cluster_lights": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p]),

@@ -403,3 +403,19 @@ def nvc_adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
                                                 float(lr if lr_end is None else lr_end), int(lr_decay_steps),
                                                 float(beta1), float(beta2), float(eps), int(bool(zero_grad)),
                                                 _stream(stream)))
+
+
+def nvc_forward_f64(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, w: torch.Tensor, pos: torch.Tensor,
+                    labels=None, loss: int = 0, z=None, masks=None, loss_out=None, stream=None) -> None:
+    """FP64 forward pass (gradient checks): logits z [n][n_out], branch masks [n][n_hidden][ceil(width/8)],
+    per-point losses and their mean in loss_out [n + 1] (with labels)."""
+    n = pos.shape[0]
+    pt = _ptr(table, "table", torch.float64, (grid.n_levels, 1 << grid.log2_T, grid.n_feat))
+    pw = _ptr(w, "w", torch.float64, (nvc_mlp_param_count(mlp),))
+    pp = _ptr(pos, "pos", torch.float32, (n, 3))
+    pl = _ptr(labels, "labels", torch.uint8, (n, mlp.n_out), optional=True)
+    pz = _ptr(z, "z", torch.float64, (n, mlp.n_out), optional=True)
+    pm = _ptr(masks, "masks", torch.uint8, (n, mlp.n_hidden, (mlp.width + 7) // 8), optional=True)
+    po = _ptr(loss_out, "loss_out", torch.float64, (n + 1,), optional=labels is None)
+    _lib.check("nvc_forward_f64", _lib.load().nvc_forward_f64(ctypes.byref(grid), ctypes.byref(mlp), pt, pw, pp, int(n),
+                                                              pl, int(loss), pz, pm, po, _stream(stream)))

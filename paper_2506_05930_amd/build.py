@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["capi.cpp", "mlp.hip", "encode.hip", "sampling.hip", "train.hip", "route.hip", "labels.hip", "adam.hip",
-           "clustered.hip", "noalloc.hip"]
+           "clustered.hip", "noalloc.hip", "check_f64.hip"]
 ARCH = os.environ.get("NVC_OFFLOAD_ARCH", "gfx950")
 
 

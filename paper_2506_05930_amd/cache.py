@@ -386,3 +386,29 @@ class NVCFunction(torch.autograd.Function):
                            pos_unit.shape[0], None, dvis.contiguous().float(), cache.loss, ctx.grad_scale,
                            g_table, g_w, None, cache.workspace)
         return None, g_table, g_w, None, None
+
+
+class NVCLossFunction(torch.autograd.Function):
+    """loss = the training loss of a labelled batch (Sec. 3.3-3.4) with gradients for the table and the FP32
+    master weights: the library's training kernel in labelled mode.  forward runs nvc_train_step once on a
+    private packed copy of `w` and keeps the gradients it returns; backward scales them by the incoming
+    gradient.  labels: uint8 [n][n_out]; the loss kind is the cache's (BCE or L2)."""
+
+    @staticmethod
+    def forward(ctx, pos_unit, table, w, labels, cache: NVCache, grad_scale: float = 0.0):
+        packed = torch.empty(api.nvc_mlp_packed_bytes(cache.mlp), dtype=torch.uint8, device=pos_unit.device)
+        api.nvc_pack_mlp(cache.mlp, w.detach().contiguous(), packed)
+        g_table = torch.zeros_like(table, dtype=torch.float32)
+        g_w = torch.zeros_like(w, dtype=torch.float32)
+        loss = torch.zeros(1, dtype=torch.float32, device=pos_unit.device)
+        cache._ensure_workspace(pos_unit.shape[0])
+        api.nvc_train_step(cache.grid, cache.mlp, table.detach().contiguous(), packed, pos_unit, None,
+                           pos_unit.shape[0], labels, None, cache.loss, grad_scale, g_table, g_w, loss,
+                           cache.workspace)
+        ctx.save_for_backward(g_table, g_w)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g_table, g_w = ctx.saved_tensors
+        return None, g_table * grad_out, g_w * grad_out, None, None, None

@@ -314,6 +314,22 @@ int nvc_counters_advance(nvc_counters* ctr, void* stream) {
     return hip_status(launch_counters_advance(&ctr->frame, &ctr->step, (hipStream_t)stream));
 }
 
+int nvc_forward_f64(const nvc_grid* grid, const nvc_mlp* mlp, const double* table, const double* w,
+                    const float* pos, int64_t n, const uint8_t* labels, int32_t loss, double* z, uint8_t* masks,
+                    double* loss_out, void* stream) {
+    GridHost g{};
+    NetShape s{};
+    const int st = check_net(grid, mlp, &g, &s);
+    if (st) return st;
+    if (n < 0 || n > ((int64_t)1 << 20)) return NVC_ERR_SHAPE;
+    if (labels && loss != NVC_LOSS_BCE && loss != NVC_LOSS_L2) return NVC_ERR_SHAPE;
+    if (n == 0) return NVC_OK;
+    if (!table || !w || !pos) return NVC_ERR_NULL;
+    if (labels && !loss_out) return NVC_ERR_NULL;
+    return hip_status(launch_forward_f64(g, s, table, w, pos, n, labels, loss, z, masks, labels ? loss_out : nullptr,
+                                         (hipStream_t)stream));
+}
+
 int nvc_graph_begin(void* stream) {
     if (!stream) return NVC_ERR_NULL;       // the legacy default stream cannot be captured
     return hip_status(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));

@@ -110,6 +110,9 @@ hipError_t launch_clustered_sample(const void* vis, int vis_dtype, int64_t n, in
                                    const uint32_t* frame_dev, int32_t* idx, float* weight, int32_t* cluster,
                                    const uint8_t* mask, nvc_reservoir* res, hipStream_t st);
 void cluster_lights_host(const float* lights, int n, int k, int iters, int32_t* offsets, int32_t* members);
+hipError_t launch_forward_f64(const GridHost& g, const NetShape& s, const double* table, const double* w,
+                              const float* pos, int64_t n, const uint8_t* labels, int loss, double* z,
+                              uint8_t* masks, double* loss_out, hipStream_t st);
 // frame += 1, step += 1 of the device counters {uint32 frame; int32 step}.
 hipError_t launch_counters_advance(uint32_t* frame_dev, int32_t* step_dev, hipStream_t st);
 

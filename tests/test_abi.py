@@ -295,3 +295,18 @@ def test_noalloc_pixel_selection_validates_before_launching(lib):
     assert lib.nvc_select_pixels_noalloc(0, 0, None, 100, 0, None, None) == 0      # empty batch: no-op
     hdr = open(HEADER).read()
     assert f"#define NVC_SELECT_PIXELS_NOALLOC_MAX_PIX (1 << {big.bit_length() - 1})" in hdr
+
+
+def test_fp64_forward_validates_before_launching(lib):
+    P = ctypes.c_void_p(16)
+    N = None
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())
+    f = lib.nvc_forward_f64
+    assert f(None, mm, P, P, P, 10, N, 0, P, N, N, N) == _lib.NVC_ERR_NULL
+    assert f(gg, ctypes.byref(m(n_in=30)), P, P, P, 10, N, 0, P, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert f(gg, mm, P, P, P, -1, N, 0, P, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert f(gg, mm, P, P, P, (1 << 20) + 1, N, 0, P, N, N, N) == _lib.NVC_ERR_SHAPE
+    assert f(gg, mm, P, P, P, 10, P, 7, P, N, P, N) == _lib.NVC_ERR_SHAPE          # unknown loss
+    assert f(gg, mm, None, P, P, 10, N, 0, P, N, N, N) == _lib.NVC_ERR_NULL
+    assert f(gg, mm, P, P, P, 10, P, 0, P, N, None, N) == _lib.NVC_ERR_NULL        # labels without loss_out
+    assert f(gg, mm, None, None, None, 0, N, 0, N, N, N, N) == 0                   # n == 0 is a no-op

@@ -314,8 +314,9 @@ def test_train_gradients_match_oracle(wl_name, dtype, tol, batch, loss):
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 3e-2)])
 def test_train_gradients_2pow14_samples(dtype, tol):
-    """The 1080p network's gradient pass on 2^14 samples (many samples per table partition and per
-    training block, several persistent iterations per block) against the oracle."""
+    """The 1080p network's gradient pass on 2^14 samples (many samples per table partition; 256 block
+    iterations of 64 samples, at most one per resident training block) against the oracle.  The production
+    batch, with several persistent iterations per block, is in test_gpu_fullsize.py."""
     wl = p1080()
     p = params(wl)
     cache = make_cache(wl, p, dtype=dtype)
