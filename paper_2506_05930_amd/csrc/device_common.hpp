@@ -445,7 +445,7 @@ __device__ inline void wrs_weight(const float4& l, float px, float py, float pz,
     } else {
         f = __fdiv_rn(l.w, d2);
     }
-    w = f * fmaxf(v, vis_floor);
+    w = f * (v >= vis_floor ? v : vis_floor);           // max(v, floor), a NaN v taken as the floor
 }
 
 }  // namespace nvc
