@@ -134,7 +134,7 @@ def test_plain_pick_reservoir_and_mask(scene):
     sel = rng.choice(scene["pos"].shape[0], n, replace=False)
     pos, nrm = scene["pos"][sel], scene["nrm"][sel]
     lights = scene["lights"][:m]
-    vis = t(rng.uniform(0, 1, (n, m)).astype(np.float32)).half()
+    vis = t(rng.uniform(0, 1, (n, m)).astype(np.float16))
     outs = {}
     for masked in (False, True):
         mk = t((rng.uniform(size=n) > 0.3).astype(np.uint8)) if masked else None
