@@ -317,3 +317,48 @@ def test_pipeline_train_step_matches_torch_autograd_and_adam():
                                 seed=5, frame=0, batch=batch, lr=0.02)
     untouched = first["grads"]["g_table"] == 0
     assert untouched.any() and np.array_equal(first["table"][untouched], table.astype(np.float64)[untouched])
+
+
+def test_l2_loss_leaves_confident_misses_bce_does_not():
+    """Why the paper's L2 loss can raise the mean variance of the light estimator (Sec. 3.1 Fig. "bias":
+    fireflies) while BCE lowers it, on the oracle alone.  The paper's network and schedule (ten levels of
+    four features, 40-32-32-32 leaky ReLU, rate 0.05 decaying) trained for 25 steps of 2048 screen samples
+    with each loss.  With L2 the gradient 2 (v - y) v (1 - v) vanishes on a visible light predicted near
+    zero, so such confident misses persist; clamped to 0.001 they get a tiny pick probability and their
+    1/p term dominates the second moment.  With BCE (gradient v - y) they are rare."""
+    from oracle import estimator, lighting, pipeline, shadow
+    from workloads import box_scene, get_workload, init_params
+    sc = box_scene(0, 96, 54, 64, 32, 256)
+    n = sc["pos"].shape[0]
+    sub = np.random.default_rng(5).choice(n, 1024, replace=False)
+    V = shadow.labels_fp32(sc["pos"][sub], sc["lights"], sc["spheres"]).astype(np.float64)
+    f = lighting.unshadowed_weight(sc["pos"][sub], sc["nrm"][sub], sc["lights"])
+    ok = (f * V).sum(1) > 0
+    out = {}
+    for loss in ("l2", "bce"):
+        wl = get_workload("paper_1080p", loss=loss)
+        p = init_params(wl.init_seed, wl.grid, wl.mlp, init=wl.init)
+        state, tab, ws = None, p["table"], p["weights"]
+        for s in range(25):
+            lr = training.learning_rate(s + 1, wl.lr, wl.lr_end, wl.lr_decay_steps)
+            r = pipeline.train_step(sc["pos_unit"], sc["pos"], sc["lights"], sc["spheres"], tab, ws,
+                                    wl.grid.base_res, wl.grid.growth, seed=2, frame=s, batch=2048, adam_state=state,
+                                    lr=lr, loss=loss, act="leaky", slope=0.01)
+            state, tab, ws = r["adam"], r["table"], r["weights"]
+        v = pipeline.infer(sc["pos_unit"][sub], tab.astype(np.float32), [w.astype(np.float32) for w in ws],
+                           wl.grid.base_res, wl.grid.growth, act="leaky", slope=0.01)
+        w = f * np.maximum(v, 1e-3)
+        pc = w / w.sum(1, keepdims=True)
+        pn = f / f.sum(1, keepdims=True)
+        _, Ec, vc, _ = estimator.moments(f[ok], V[ok], pc[ok])
+        mu, _, vn, _ = estimator.moments(f[ok], V[ok], pn[ok])
+        assert np.allclose(Ec, mu, rtol=1e-12)                     # the clamp keeps it unbiased
+        miss = (V[ok] == 1) & (v[ok] < 0.01) & (f[ok] > 0)
+        c = f[ok] * V[ok]
+        second = np.where(pc[ok] > 0, c * c / np.where(pc[ok] > 0, pc[ok], 1.0), 0.0)
+        out[loss] = {"miss": miss.mean(), "miss_share": (second * miss).sum() / second.sum(),
+                     "ratio": vc.mean() / vn.mean(), "median": np.median(vc[vn > 0] / vn[vn > 0])}
+    l2, bce = out["l2"], out["bce"]
+    assert l2["miss"] > 10 * bce["miss"] and l2["miss_share"] > 0.5
+    assert l2["ratio"] > 1.0 > bce["ratio"]
+    assert l2["median"] < 0.5 and bce["median"] < 0.5               # the typical pixel gains with either loss
