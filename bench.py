@@ -50,6 +50,9 @@ def parse():
                     help="skip the extra timed frames on the row-major G-buffer (reported beside the Z-order ones)")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the serial per-stage pass (every launch of the run is then a timed-style frame)")
+    ap.add_argument("--fused-labels", action="store_true",
+                    help="label the training samples inside the training kernel (nvc_train_step_shadow) instead "
+                         "of with the separate label kernel")
     ap.add_argument("--loop", type=int, default=0,
                     help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
                          "moving) and print its per-frame report")
@@ -426,6 +429,9 @@ def main():
         if not nw:
             return
         api.nvc_world_samples(cache.seed, frame, wl.world_box, SCENE_EXTENT, wpos, wunit, st)
+        if fused:
+            cache.gradients_shadow(wunit, wpos, lights, spheres, batch=nw, stream=st)
+            return
         if clustered:
             api.nvc_shadow_labels_clustered(wpos, None, lights, cache.cl_offsets, cache.cl_members, spheres,
                                             cache.seed, frame, wlab, st)
@@ -433,12 +439,22 @@ def main():
             api.nvc_shadow_labels(wpos, None, lights, spheres, wlab, st)
         cache.gradients(wunit, labels=wlab, batch=nw, stream=st)
 
+    fused = args.fused_labels and not clustered
+
     def do_labels(frame, st=None):
+        if fused:
+            return
         if clustered:
             api.nvc_shadow_labels_clustered(pos, pix, lights, cache.cl_offsets, cache.cl_members, spheres, cache.seed,
                                             frame, labels, st)
         else:
             api.nvc_shadow_labels(pos, pix, lights, spheres, labels, st)
+
+    def do_gradients(st=None):
+        if fused:
+            cache.gradients_shadow(pos_unit, pos, lights, spheres, pix=pix, batch=B, stream=st)
+        else:
+            cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=st)
 
     def step(frame, ev=None, kev=None):
         """One frame.  Timed frames run the training half (pixels, labels, gradients) on a second
@@ -449,7 +465,7 @@ def main():
             side.wait_stream(stream)
             api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws, side)
             do_labels(frame, side)
-            cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=side)
+            do_gradients(side)
             do_world(frame, side)
             if kev is not None:
                 kev[0].record(stream)
@@ -471,7 +487,7 @@ def main():
         ev[3].record(stream)
         do_labels(frame)
         ev[4].record(stream)
-        cache.gradients(pos_unit, labels=labels, pix=pix, batch=B)
+        do_gradients()
         do_world(frame)
         ev[5].record(stream)
         cache.adam()
@@ -577,7 +593,8 @@ def main():
                    "train_batch": B, **({"world_batch": wl.world_batch} if wl.world_batch else {}),
                    "grid": f"L{wl.grid.n_levels} F{wl.grid.n_feat} T2^{wl.grid.log2_T}",
                    "mlp": f"{wl.mlp.n_in}-{wl.mlp.width}x{wl.mlp.n_hidden}-{wl.mlp.n_out}",
-                   "pixel_order": args.order},
+                   "pixel_order": args.order,
+                   "labels": "inside the training kernel" if fused else "label kernel"},
         "ms_per_frame": ms_per_step,
         "ms_per_frame_rowmajor": None if rows_ms is None else round(rows_ms, 4),
         "streams": "training half on a second stream beside inference + WRS; stage_ms from a serial pass",

@@ -372,6 +372,33 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                    float* g_table, float* g_w, float* loss_out,
                    void* workspace, int64_t workspace_bytes, void* stream);
 
+/* nvc_train_step in labelled mode with the shadow labels computed inside the
+ * training kernel instead of read from memory (Sec. 3.4: each training example
+ * pairs a position with the visibility of every light, from one shadow ray per
+ * light; Sec. 4.4 and Table "perf_breakdown" fuse data generation into the
+ * training pass).  The label of sample b and light j is the one
+ * nvc_shadow_labels gives for scene-space position pos_scene[pix[b]] (pos_scene
+ * indexed like pos; pix may be NULL), lights [m][4] and spheres [n_spheres][4]
+ * (the same FP32 decision), and the network has one output per light
+ * (m == mlp->n_out).  Each wave culls the spheres against the bundle of its 16
+ * samples' segments to every light before the exact tests.  labels_out
+ * (uint8 [batch][m], or NULL) receives the labels.  Limits: 1 <= m <=
+ * NVC_TRAIN_SHADOW_MAX_LIGHTS, 0 <= n_spheres <= NVC_TRAIN_SHADOW_MAX_SPHERES
+ * (else NVC_ERR_SHAPE); networks with more than 32 outputs have no such kernel,
+ * nor shapes whose activations, scatter cursors, lights and spheres overflow the
+ * 160 KiB of LDS of a compute unit (NVC_ERR_UNSUPPORTED).  The pass runs on the
+ * grid of nvc_train_step, so its gradients and loss equal those of
+ * nvc_train_step given the same labels, bit for bit; the workspace is
+ * nvc_train_workspace_bytes for the same network and batch.  Everything else as
+ * nvc_train_step. */
+#define NVC_TRAIN_SHADOW_MAX_LIGHTS 32
+#define NVC_TRAIN_SHADOW_MAX_SPHERES 512
+int nvc_train_step_shadow(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
+                          const float* pos, const float* pos_scene, const int32_t* pix, int64_t batch,
+                          const float* lights, int32_t m, const float* spheres, int32_t n_spheres, int32_t loss,
+                          float grad_scale, float* g_table, float* g_w, float* loss_out, uint8_t* labels_out,
+                          void* workspace, int64_t workspace_bytes, void* stream);
+
 /* One Adam step (Sec. 3.4; Kingma & Ba) over `count` FP32 parameters, dense:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
  *   p -= (lr_t / (1 - b1^step)) * m / (sqrt(v) / sqrt(1 - b2^step) + eps)

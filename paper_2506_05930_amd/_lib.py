@@ -23,6 +23,8 @@ NVC_F32, NVC_F16, NVC_BF16 = 0, 1, 2
 NVC_ACT_RELU, NVC_ACT_LEAKY = 0, 1
 NVC_LOSS_BCE, NVC_LOSS_L2 = 0, 1
 NVC_SELECT_PIXELS_NOALLOC_MAX_PIX = 1 << 23
+NVC_TRAIN_SHADOW_MAX_LIGHTS = 32
+NVC_TRAIN_SHADOW_MAX_SPHERES = 512
 
 EXPORTS = [
     "nvc_version", "nvc_status_string", "nvc_grid_levels", "nvc_mlp_param_count", "nvc_mlp_packed_bytes",
@@ -31,7 +33,7 @@ EXPORTS = [
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
     "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered", "nvc_world_samples",
     "nvc_graph_begin", "nvc_graph_end", "nvc_graph_launch", "nvc_graph_destroy", "nvc_select_pixels_noalloc",
-    "nvc_forward_f64",
+    "nvc_forward_f64", "nvc_train_step_shadow",
 ]
 
 
@@ -75,6 +77,9 @@ _SIGS = {
     "nvc_train_step": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                  c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int64, c_void_p]),
+    "nvc_train_step_shadow": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32, c_int32, c_float,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),
     "nvc_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_void_p, c_float, c_float,
                            c_int32, c_float, c_float, c_float, c_int32, c_void_p]),
     "nvc_counters_advance": (c_int32, [c_void_p, c_void_p]),

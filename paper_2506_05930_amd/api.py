@@ -391,6 +391,36 @@ def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torc
                                                             pw, po, pws, wsb, _stream(stream)))
 
 
+def nvc_train_step_shadow(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor,
+                          pos_scene: torch.Tensor, pix, batch: int, lights: torch.Tensor, spheres: torch.Tensor,
+                          loss: int, grad_scale: float, g_table: torch.Tensor, g_w: torch.Tensor, loss_out,
+                          labels_out, workspace: torch.Tensor, stream=None) -> None:
+    """Labelled training gradients with the shadow labels computed inside the training kernel
+    (pos_scene: the scene-space positions, indexed like pos; labels_out [batch][m] uint8 or None)."""
+    tshape = (grid.n_levels, 1 << grid.log2_T, grid.n_feat)
+    pt = _ptr(table, "table", torch.float32, tshape)
+    pk = _ptr(packed, "packed")
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    ps = _ptr(pos_scene, "pos_scene", torch.float32, (pos.shape[0], 3))
+    px = _ptr(pix, "pix", torch.int32, (batch,), optional=True)
+    if pix is None and pos.shape[0] < batch:
+        raise ValueError("pos has fewer rows than the batch")
+    m = lights.shape[0]
+    pl = _ptr(lights, "lights", torch.float32, (m, 4))
+    n_s = spheres.shape[0]
+    psp = _ptr(spheres, "spheres", torch.float32, (n_s, 4))
+    pg = _ptr(g_table, "g_table", torch.float32, tshape)
+    pw = _ptr(g_w, "g_w", torch.float32, (nvc_mlp_param_count(mlp),))
+    po = _ptr(loss_out, "loss_out", torch.float32, (1,), optional=True)
+    plo = _ptr(labels_out, "labels_out", torch.uint8, (batch, m), optional=True)
+    pws = _ptr(workspace, "workspace")
+    wsb = workspace.numel() * workspace.element_size()
+    _lib.check("nvc_train_step_shadow",
+               _lib.load().nvc_train_step_shadow(ctypes.byref(grid), ctypes.byref(mlp), pt, pk, pp, ps, px,
+                                                 int(batch), pl, int(m), psp, int(n_s), int(loss),
+                                                 float(grad_scale), pg, pw, po, plo, pws, wsb, _stream(stream)))
+
+
 def nvc_adam(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float,
              beta1: float, beta2: float, eps: float, zero_grad: bool = False, stream=None, ctr=None,
              lr_end: float | None = None, lr_decay_steps: int = 0) -> None:

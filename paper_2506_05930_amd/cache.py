@@ -27,7 +27,8 @@ from ._lib import NVC_LOSS_BCE, NVC_LOSS_L2
 class NVCache:
     def __init__(self, grid_cfg, mlp_cfg, table, weights, device="cuda", seed: int = 2, lr: float = 1e-2,
                  beta1: float = 0.9, beta2: float = 0.99, eps: float = 1e-8, loss: str = "bce",
-                 vis_floor: float = 1e-3, max_batch: int = 0, lr_end: float | None = None, lr_decay_steps: int = 0):
+                 vis_floor: float = 1e-3, max_batch: int = 0, lr_end: float | None = None, lr_decay_steps: int = 0,
+                 fused_labels: bool = False):
         self.grid = api.make_grid(grid_cfg.n_levels, grid_cfg.n_feat, grid_cfg.log2_T, grid_cfg.base_res,
                                   grid_cfg.growth)
         self.mlp = api.make_mlp(mlp_cfg.n_in, mlp_cfg.width, mlp_cfg.n_hidden, mlp_cfg.n_out, mlp_cfg.act,
@@ -39,6 +40,9 @@ class NVCache:
         self.lr_end, self.lr_decay_steps = lr_end, lr_decay_steps     # linear decay of Sec. 3.4 (0: constant)
         self.loss = {"bce": NVC_LOSS_BCE, "l2": NVC_LOSS_L2}[loss]
         self.vis_floor = vis_floor
+        # training pixels labelled inside the training kernel (nvc_train_step_shadow) instead of by the
+        # separate label kernel; same labels and gradients
+        self.fused_labels = bool(fused_labels)
         self.table = torch.as_tensor(np.ascontiguousarray(table), dtype=torch.float32).to(self.device)
         flat = np.concatenate([np.asarray(w, np.float32).reshape(-1) for w in weights]) \
             if isinstance(weights, (list, tuple)) else np.asarray(weights, np.float32)
@@ -142,6 +146,18 @@ class NVCache:
                            self.loss, grad_scale, self.g_table, self.g_w, self.loss_buf if labels is not None else None,
                            self.workspace, stream)
 
+    def gradients_shadow(self, pos_unit, pos_scene, lights, spheres, pix=None, batch: int | None = None,
+                         grad_scale: float = 0.0, labels_out=None, stream=None):
+        """gradients() with the shadow labels of pos_scene (indexed like pos_unit) computed inside the
+        training kernel: one network output per light (at most 32 lights, 512 spheres); labels_out
+        (uint8 [batch][m]) receives them if given."""
+        if batch is None:
+            batch = pix.shape[0] if pix is not None else pos_unit.shape[0]
+        self._ensure_workspace(batch)
+        api.nvc_train_step_shadow(self.grid, self.mlp, self.table, self.packed, pos_unit, pos_scene, pix, batch,
+                                  lights, spheres, self.loss, grad_scale, self.g_table, self.g_w, self.loss_buf,
+                                  labels_out, self.workspace, stream)
+
     def adam(self, stream=None, ctr=None):
         """One Adam step on table and weights (gradients cleared), then repack the weights.
 
@@ -165,9 +181,13 @@ class NVCache:
         if self.clustered:
             api.nvc_shadow_labels_clustered(pos_scene, bufs["pix"], lights, self.cl_offsets, self.cl_members, spheres,
                                             self.seed, frame, bufs["labels"], stream, ctr=ctr)
+            self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
+        elif self.fused_labels:
+            self.gradients_shadow(pos_unit, pos_scene, lights, spheres, pix=bufs["pix"], batch=batch,
+                                  labels_out=bufs["labels"], stream=stream)
         else:
             api.nvc_shadow_labels(pos_scene, bufs["pix"], lights, spheres, bufs["labels"], stream)
-        self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
+            self.gradients(pos_unit, labels=bufs["labels"], pix=bufs["pix"], batch=batch, stream=stream)
         if getattr(self, "world", None) is not None and self.world[0] > 0:
             nw, box, extent = self.world
             if "wpos" not in bufs:

@@ -296,6 +296,32 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                                    g_w, loss_out, workspace, (hipStream_t)stream));
 }
 
+int nvc_train_step_shadow(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
+                          const float* pos, const float* pos_scene, const int32_t* pix, int64_t batch,
+                          const float* lights, int32_t m, const float* spheres, int32_t n_spheres, int32_t loss,
+                          float grad_scale, float* g_table, float* g_w, float* loss_out, uint8_t* labels_out,
+                          void* workspace, int64_t workspace_bytes, void* stream) {
+    GridHost g{};
+    NetShape s{};
+    const int st = check_net(grid, mlp, &g, &s);
+    if (st) return st;
+    if (batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
+    if (loss != NVC_LOSS_BCE && loss != NVC_LOSS_L2) return NVC_ERR_SHAPE;
+    if (!(grad_scale >= 0.0f) || !isfinite(grad_scale)) return NVC_ERR_SHAPE;
+    if (m != s.n_out || m < 1 || m > NVC_TRAIN_SHADOW_MAX_LIGHTS) return NVC_ERR_SHAPE;
+    if (n_spheres < 0 || n_spheres > NVC_TRAIN_SHADOW_MAX_SPHERES) return NVC_ERR_SHAPE;
+    if (!train_shadow_supported(g, s, batch, n_spheres)) return NVC_ERR_UNSUPPORTED;
+    if (batch == 0) return NVC_OK;
+    if (!table || !packed || !pos || !pos_scene || !lights || !g_table || !g_w) return NVC_ERR_NULL;
+    if (n_spheres > 0 && !spheres) return NVC_ERR_NULL;
+    const int64_t need = train_workspace_bytes(g, s, batch);
+    if (!workspace || workspace_bytes < need) return NVC_ERR_WORKSPACE;
+    const PackPlan p = make_pack_plan(s);
+    const ShadowArgs sh{pos_scene, lights, m, spheres, n_spheres, labels_out};
+    return hip_status(launch_train_shadow(g, s, p, table, packed, pos, pix, batch, sh, loss, grad_scale, g_table, g_w,
+                                          loss_out, workspace, (hipStream_t)stream));
+}
+
 int nvc_adam(float* p, float* g, float* m, float* v, int64_t count, int32_t step, const nvc_counters* ctr, float lr,
              float lr_end, int32_t lr_decay_steps, float beta1, float beta2, float eps, int32_t zero_grad,
              void* stream) {

@@ -97,6 +97,20 @@ hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& pl
                         const void* packed, const float* pos, const int32_t* pix, int64_t batch,
                         const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
                         float* g_w, float* loss_out, void* workspace, hipStream_t st);
+// Shadow-label inputs of the training pass that computes its labels in the kernel.
+struct ShadowArgs {
+    const float* pos_scene;   // [*][3] scene units, indexed like the unit-cube positions
+    const float* lights;      // [n_lights][4]
+    int n_lights;
+    const float* spheres;     // [n_spheres][4]
+    int n_spheres;
+    uint8_t* labels_out;      // [batch][n_lights] or NULL
+};
+bool train_shadow_supported(const GridHost& g, const NetShape& s, int64_t batch, int n_spheres);
+hipError_t launch_train_shadow(const GridHost& g, const NetShape& s, const PackPlan& plan, const float* table,
+                               const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                               const ShadowArgs& sh, int loss, float grad_scale, float* g_table, float* g_w,
+                               float* loss_out, void* workspace, hipStream_t st);
 hipError_t launch_adam(float* p, float* g, float* m, float* v, int64_t count, int step, const int32_t* step_dev,
                        float lr, float lr_end, int lr_decay_steps, float beta1, float beta2, float eps, int zero_grad,
                        hipStream_t st);

@@ -67,7 +67,24 @@ struct TrainArgs {
     int act;
     float slope;
     RouteDev route;       // routed table scatter (route.enabled == 0: direct atomics)
+    // shadow labels computed in the kernel (SHADOW instantiations): scene-space positions (indexed like
+    // pos), lights [n_lights][4] (one network output per light), spheres [n_spheres][4] (c, r);
+    // labels_out [batch][n_out] receives them if not NULL
+    const float* pos_scene;
+    const float* lights;
+    int n_lights;
+    const float* spheres;
+    int n_spheres;
+    uint8_t* labels_out;
 };
+
+// Largest sphere count and light count of the in-kernel shadow labels (LDS: 24 B per sphere, 16 B per light).
+constexpr int kShadowMaxSpheres = NVC_TRAIN_SHADOW_MAX_SPHERES;
+constexpr int kShadowMaxLights = NVC_TRAIN_SHADOW_MAX_LIGHTS;
+
+__host__ __device__ constexpr size_t shadow_smem_bytes(int n_spheres) {
+    return (size_t)n_spheres * 24 + (size_t)kShadowMaxLights * 16 + 16;
+}
 
 // LDS of one block, in the matrix-core dtype, [neuron][sample] with row stride
 // SD: the inputs h_0 .. h_{NL-1} of every layer (written by the forward pass,
@@ -188,8 +205,108 @@ __device__ inline void accumulate_dw(const typename Mma<DT>::elem* D, const type
     }
 }
 
-template <class C>
-__global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
+// Shadow labels of the wave's 16 samples for the lane's lights 16 ob + 4 grp + i (ob < NOB, i < 4),
+// decided in FP32 exactly as by the separate label kernel (the operation order of nvc.h):
+// returns bit 4 ob + i set iff that light is visible from the lane's sample.  The spheres are
+// culled against the bundle of the 16 segments to each light (a conservative capsule test, margin
+// 1e-3 (1 + scene scale)); a sphere that survives for some light of some lane is tested exactly by
+// every lane for each of its lights that it may reach.
+template <int NOB>
+__device__ inline uint32_t shadow_bits(const TrainArgs& a, const float4* __restrict__ SL, const float4* __restrict__ SS,
+                                       const float* __restrict__ SR, const uint32_t* __restrict__ SIN, float scene_scale,
+                                       int lane, int grp, float px, float py, float pz) {
+    const int m = a.n_lights, ns = a.n_spheres;
+    // bundle of the wave's 16 samples (every 16-lane row holds the same ones)
+    float mn[3] = {px, py, pz}, mx[3] = {px, py, pz};
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = fminf(mn[k], __shfl_xor(mn[k], off));
+            mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
+        }
+    const float cx = 0.5f * (mn[0] + mx[0]), cy = 0.5f * (mn[1] + mx[1]), cz = 0.5f * (mn[2] + mx[2]);
+    const float hx = 0.5f * (mx[0] - mn[0]), hy = 0.5f * (mx[1] - mn[1]), hz = 0.5f * (mx[2] - mn[2]);
+    const float rho = sqrtf(hx * hx + hy * hy + hz * hz) * 1.0001f;
+    const float scale = fmaxf(scene_scale, fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz))) + rho);
+    const float margin = 1e-3f * (1.0f + scale);
+    const bool cull_ok = isfinite(rho) && isfinite(cx) && isfinite(cy) && isfinite(cz) && isfinite(margin);
+    // the lane's segments: light li = 16 ob + 4 grp + i
+    float dx[NOB][4], dy[NOB][4], dz[NOB][4], dd[NOB][4];
+#pragma unroll
+    for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int li = min(16 * ob + 4 * grp + i, m - 1);
+            const float4 l = SL[li];
+            dx[ob][i] = l.x - px;
+            dy[ob][i] = l.y - py;
+            dz[ob][i] = l.z - pz;
+            dd[ob][i] = (dx[ob][i] * dx[ob][i] + dy[ob][i] * dy[ob][i]) + dz[ob][i] * dz[ob][i];
+        }
+    uint32_t occ = 0;
+    for (int c0 = 0; c0 < ns; c0 += 64) {
+        // cull: lane j takes sphere c0 + j against every light's bundle capsule
+        const int s = c0 + lane;
+        const bool in_range = s < ns;
+        const float4 sc = in_range ? SS[s] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const uint32_t s_in = in_range ? SIN[s] : 0u;
+        uint32_t lmask = 0;
+        if (in_range) {
+            if (!cull_ok) {
+                lmask = m >= 32 ? 0xFFFFFFFFu : ((1u << m) - 1u);
+            } else {
+                const float ox = sc.x - cx, oy = sc.y - cy, oz = sc.z - cz;
+                const float lim = SR[s] + rho + margin;
+                const float lim2 = lim * lim;
+                for (int l = 0; l < m; ++l) {
+                    const float4 L = SL[l];
+                    const float gx = L.x - cx, gy = L.y - cy, gz = L.z - cz;
+                    const float gg = gx * gx + gy * gy + gz * gz;
+                    const float ginv = gg > 0.0f ? 1.0f / gg : 0.0f;
+                    const float t = fminf(fmaxf((ox * gx + oy * gy + oz * gz) * ginv, 0.0f), 1.0f);
+                    const float qx = ox - t * gx, qy = oy - t * gy, qz = oz - t * gz;
+                    if (qx * qx + qy * qy + qz * qz <= lim2) lmask |= 1u << l;
+                }
+            }
+        }
+        uint64_t surv = __ballot(lmask != 0u);
+        while (surv) {
+            const int j = __builtin_ctzll(surv);
+            surv &= surv - 1;
+            const uint32_t ls = (uint32_t)__builtin_amdgcn_readlane((int)lmask, j);
+            const float sx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc.x), j));
+            const float sy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc.y), j));
+            const float sz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc.z), j));
+            const float sw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sc.w), j));
+            const uint32_t ib = (uint32_t)__builtin_amdgcn_readlane((int)s_in, j);
+            const float ox = sx - px, oy = sy - py, oz = sz - pz;
+            const float cc = ((ox * ox + oy * oy) + oz * oz) - sw;
+#pragma unroll
+            for (int ob = 0; ob < NOB; ++ob)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    // lights 16 ob + 4 g + i of the four lane groups g
+                    const uint32_t slot_lights = (0x1111u << (16 * ob + i)) & 0xFFFFFFFFu;
+                    if (!(ls & slot_lights)) continue;
+                    const float bb = (ox * dx[ob][i] + oy * dy[ob][i]) + oz * dz[ob][i];
+                    const uint32_t near_p = bb <= 0.0f;
+                    const uint32_t near_l = (bb >= dd[ob][i]) & ~near_p;
+                    const uint32_t mid = ~(near_p | near_l) & 1u;
+                    const int li = 16 * ob + 4 * grp + i;
+                    const uint32_t o = (near_p & (uint32_t)(cc < 0.0f)) | (near_l & (ib >> (li & 31))) |
+                                       (mid & (uint32_t)(cc * dd[ob][i] < bb * bb));
+                    occ |= (o & 1u) << (4 * ob + i);
+                }
+        }
+    }
+    return ~occ & ((1u << (4 * NOB)) - 1u);
+}
+
+// The in-kernel labels hold the lane's light segments across the sphere loop; the register budget of two
+// waves per SIMD keeps the occupancy of the plain kernel.
+template <class C, bool SHADOW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHADOW ? 2 : 1))) void train_kernel(TrainArgs a) {
     constexpr int DT = C::DT;
     using M = Mma<DT>;
     using E = typename M::elem;
@@ -215,6 +332,45 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
             cursor[i] = a.route.base[i] + a.route.offsets[(int64_t)i * gridDim.x + blockIdx.x];
         __syncthreads();
     }
+    // In-kernel shadow labels: lights, spheres (c, r^2), radii and light-inside bits in LDS after the cursors.
+    float4* SL = nullptr;
+    float4* SS = nullptr;
+    float* SR = nullptr;
+    uint32_t* SIN = nullptr;
+    float scene_scale = 0.0f;
+    if constexpr (SHADOW) {
+        const size_t off = (TS::SMEM + (a.route.enabled ? (size_t)a.route.nb * 4 : 0) + 15) / 16 * 16;
+        SL = reinterpret_cast<float4*>(smem_raw + off);
+        SS = SL + kShadowMaxLights;
+        SR = reinterpret_cast<float*>(SS + a.n_spheres);
+        SIN = reinterpret_cast<uint32_t*>(SR + a.n_spheres);
+        uint32_t* scale_bits = SIN + a.n_spheres;
+        if (threadIdx.x == 0) *scale_bits = 0u;
+        __syncthreads();
+        uint32_t my_scale = 0;
+        for (int j = threadIdx.x; j < a.n_lights; j += blockDim.x) {
+            const float lx = a.lights[4 * j + 0], ly = a.lights[4 * j + 1], lz = a.lights[4 * j + 2];
+            SL[j] = make_float4(lx, ly, lz, 0.0f);
+            my_scale = max(my_scale, __float_as_uint(fmaxf(fabsf(lx), fmaxf(fabsf(ly), fabsf(lz)))));
+        }
+        for (int q = threadIdx.x; q < a.n_spheres; q += blockDim.x) {
+            const float cx = a.spheres[4 * q + 0], cy = a.spheres[4 * q + 1], cz = a.spheres[4 * q + 2];
+            const float r = a.spheres[4 * q + 3];
+            const float rr = r * r;
+            SS[q] = make_float4(cx, cy, cz, rr);
+            SR[q] = r;
+            my_scale = max(my_scale, __float_as_uint(fmaxf(fabsf(cx), fmaxf(fabsf(cy), fabsf(cz))) + fabsf(r)));
+            uint32_t bits = 0;
+            for (int j = 0; j < a.n_lights; ++j) {
+                const float ex = cx - a.lights[4 * j + 0], ey = cy - a.lights[4 * j + 1], ez = cz - a.lights[4 * j + 2];
+                if (((ex * ex + ey * ey) + ez * ez) < rr) bits |= 1u << j;
+            }
+            SIN[q] = bits;
+        }
+        atomicMax(scale_bits, my_scale);
+        __syncthreads();
+        scene_scale = __uint_as_float(*scale_bits);
+    }
 
     float4_t acc[TS::ACC];
 #pragma unroll
@@ -237,6 +393,29 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
         const float x0 = clamp_unit(a.pos[src * 3 + 0]);
         const float x1 = clamp_unit(a.pos[src * 3 + 1]);
         const float x2 = clamp_unit(a.pos[src * 3 + 2]);
+        uint32_t shadow = 0;            // bit 4 ob + i: light 16 ob + 4 grp + i is visible (SHADOW)
+        if constexpr (SHADOW) {
+            shadow = shadow_bits<C::NOUTB>(a, SL, SS, SR, SIN, scene_scale, lane, grp, a.pos_scene[src * 3 + 0],
+                                           a.pos_scene[src * 3 + 1], a.pos_scene[src * 3 + 2]);
+            if (a.labels_out && valid) {
+                // lights 16 ob + 4 grp .. + 3 of this lane: one 4-byte store when the row keeps them aligned
+#pragma unroll
+                for (int ob = 0; ob < C::NOUTB; ++ob) {
+                    const int l0 = 16 * ob + 4 * grp;
+                    uint8_t* out = a.labels_out + b * a.n_out + l0;
+                    const uint32_t nib = (shadow >> (4 * ob)) & 0xFu;
+                    if ((a.n_out & 3) == 0 && ((uintptr_t)a.labels_out & 3u) == 0 && l0 < a.n_out) {
+                        const uint32_t word = (nib & 1u) | ((nib >> 1) & 1u) << 8 | ((nib >> 2) & 1u) << 16 |
+                                              ((nib >> 3) & 1u) << 24;
+                        *reinterpret_cast<uint32_t*>(out) = word;
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (l0 + i < a.n_out) out[i] = (uint8_t)((nib >> i) & 1u);
+                    }
+                }
+            }
+        }
         float z[TS::NOUTB_K][4];
         {
             float h0[C::NINB][4];
@@ -283,8 +462,12 @@ __global__ __launch_bounds__(256) void train_kernel(TrainArgs a) {
                     const float zv = z[ob][i];
                     const float e = exp_neg_abs(zv);
                     const float v = sigmoid_from(zv, e);
-                    if (a.labels) {
-                        const float y = (float)a.labels[b * a.n_out + li];
+                    if (SHADOW || a.labels) {
+                        float y;
+                        if constexpr (SHADOW)
+                            y = (float)((shadow >> (4 * ob + i)) & 1u);
+                        else
+                            y = (float)a.labels[b * a.n_out + li];
                         if (a.loss == 0) {
                             g = v - y;
                             loss_acc += fmaxf(zv, 0.0f) + log1pf(e) - y * zv;
@@ -499,18 +682,23 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
     }
 }
 
+// Shapes that get the in-kernel shadow labels: one 16-output block or two (at most 32 lights).
+template <class C> constexpr bool shadow_built() { return train_built<C>() && C::NOUTB <= 2; }
+
 // Persistent grid: as many blocks as stay resident (by the occupancy the
 // runtime reports for this kernel and LDS size; 2 per CU if it cannot say),
 // at most one per iteration.
 template <class C> static int train_blocks_per_cu(size_t smem) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, train_kernel<C>, 256, smem) != hipSuccess || n < 1) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, train_kernel<C, false>, 256, smem) != hipSuccess || n < 1) {
         (void)hipGetLastError();
         n = 2;
     }
     return n;
 }
 
+// The in-kernel-label variant runs on the same grid (its blocks take the same iterations, so given the
+// same labels its gradients are the plain kernel's bit for bit; blocks beyond its residency wait).
 static int train_grid(const GridHost& gh, const NetShape& s, int64_t batch, size_t cursor_bytes) {
     const int64_t iters = (batch + kTrainPts - 1) / kTrainPts;
     int per_cu = 2;
@@ -594,10 +782,24 @@ int64_t train_workspace_bytes(const GridHost& g, const NetShape& s, int64_t batc
     return ws_layout(g, n_weights(s), batch, train_grid(g, s, batch, route_cursor_bytes(rp)), rp).total;
 }
 
-hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
-                        const void* packed, const float* pos, const int32_t* pix, int64_t batch,
-                        const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
-                        float* g_w, float* loss_out, void* workspace, hipStream_t st) {
+// A shape gets the in-kernel labels if such a kernel is built and its LDS (activations, scatter cursors,
+// lights and spheres) fits the 160 KiB of a CU.
+bool train_shadow_supported(const GridHost& g, const NetShape& s, int64_t batch, int n_spheres) {
+    bool ok = false;
+    const size_t cb = route_cursor_bytes(train_route_plan(g, s, batch));
+    dispatch_config(g.n_feat, s, [&]<class C>() {
+        if constexpr (shadow_built<C>())
+            ok = (TrainShape<C>::SMEM + cb + 15) / 16 * 16 + shadow_smem_bytes(n_spheres) <= 160 * 1024;
+    });
+    return ok;
+}
+
+
+static hipError_t launch_train_impl(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
+                                    const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                                    const uint8_t* labels, const float* dvis, int loss, float grad_scale,
+                                    float* g_table, float* g_w, float* loss_out, void* workspace,
+                                    const ShadowArgs* sh, hipStream_t st) {
     TrainArgs a{};
     a.g = grid_to_dev(gh);
     a.table = table;
@@ -618,8 +820,16 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     a.labels = labels;
     a.dvis = dvis;
     a.loss = loss;
+    if (sh) {
+        a.pos_scene = sh->pos_scene;
+        a.lights = sh->lights;
+        a.n_lights = sh->n_lights;
+        a.spheres = sh->spheres;
+        a.n_spheres = sh->n_spheres;
+        a.labels_out = sh->labels_out;
+    }
     const double count = (double)batch * s.n_out;
-    if (labels) {
+    if (labels || sh) {
         const double gs = grad_scale > 0.0f ? grad_scale : count;
         a.out_mul = (float)(gs / count);
         a.final_mul = (float)(1.0 / gs);
@@ -661,8 +871,14 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     }
     err = hipErrorNotSupported;
     dispatch_config(gh.n_feat, s, [&]<class C>() {
-        if constexpr (train_built<C>()) {
-            hipLaunchKernelGGL(train_kernel<C>, dim3(G), dim3(256), TrainShape<C>::SMEM + cursor_bytes, st, a);
+        if (sh) {
+            if constexpr (shadow_built<C>()) {
+                const size_t smem = (TrainShape<C>::SMEM + cursor_bytes + 15) / 16 * 16 + shadow_smem_bytes(sh->n_spheres);
+                hipLaunchKernelGGL((train_kernel<C, true>), dim3(G), dim3(256), smem, st, a);
+                err = hipGetLastError();
+            }
+        } else if constexpr (train_built<C>()) {
+            hipLaunchKernelGGL((train_kernel<C, false>), dim3(G), dim3(256), TrainShape<C>::SMEM + cursor_bytes, st, a);
             err = hipGetLastError();
         }
     });
@@ -673,8 +889,24 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
     }
     const int slices = std::min(G, 64);
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((a.n_w + 255) / 256 + 1), slices), dim3(256), 0, st,
-                       a.ws_w, a.ws_loss, G, a.n_w, g_w, labels ? loss_out : nullptr, (float)(1.0 / count));
+                       a.ws_w, a.ws_loss, G, a.n_w, g_w, (labels || sh) ? loss_out : nullptr, (float)(1.0 / count));
     return hipGetLastError();
+}
+
+hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
+                        const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                        const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
+                        float* g_w, float* loss_out, void* workspace, hipStream_t st) {
+    return launch_train_impl(gh, s, plan, table, packed, pos, pix, batch, labels, dvis, loss, grad_scale, g_table, g_w,
+                             loss_out, workspace, nullptr, st);
+}
+
+hipError_t launch_train_shadow(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
+                               const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                               const ShadowArgs& sh, int loss, float grad_scale, float* g_table, float* g_w,
+                               float* loss_out, void* workspace, hipStream_t st) {
+    return launch_train_impl(gh, s, plan, table, packed, pos, pix, batch, nullptr, nullptr, loss, grad_scale, g_table,
+                             g_w, loss_out, workspace, &sh, st);
 }
 
 }  // namespace nvc

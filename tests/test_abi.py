@@ -310,3 +310,39 @@ def test_fp64_forward_validates_before_launching(lib):
     assert f(gg, mm, None, P, P, 10, N, 0, P, N, N, N) == _lib.NVC_ERR_NULL
     assert f(gg, mm, P, P, P, 10, P, 0, P, N, None, N) == _lib.NVC_ERR_NULL        # labels without loss_out
     assert f(gg, mm, None, None, None, 0, N, 0, N, N, N, N) == 0                   # n == 0 is a no-op
+
+
+def test_train_step_shadow_validates_before_launching(lib):
+    """The training pass with in-kernel shadow labels: one output per light, at most 32 lights and 512
+    spheres, the plain pass's workspace, required pointers; an empty batch does nothing."""
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())            # 32 outputs
+    P = ctypes.c_void_p(16)
+    N = None
+    ws = lib.nvc_train_workspace_bytes(gg, mm, 1 << 18)
+    f = lib.nvc_train_step_shadow
+
+    def call(grid=gg, mlp=mm, table=P, pos_scene=P, batch=1 << 18, lights=P, nl=32, spheres=P, ns=64, loss=0,
+             scale=0.0, g_table=P, wsp=P, wsb=ws):
+        return f(grid, mlp, table, P, P, pos_scene, N, batch, lights, nl, spheres, ns, loss, scale, g_table, P, N,
+                 N, wsp, wsb, N)
+
+    assert call(grid=None) == _lib.NVC_ERR_NULL
+    assert call(nl=31) == _lib.NVC_ERR_SHAPE                                 # one output per light
+    assert call(mlp=ctypes.byref(m(n_out=48)), nl=48) == _lib.NVC_ERR_SHAPE  # more than 32 lights
+    assert call(ns=-1) == _lib.NVC_ERR_SHAPE
+    assert call(ns=_lib.NVC_TRAIN_SHADOW_MAX_SPHERES + 1) == _lib.NVC_ERR_SHAPE
+    assert call(loss=3) == _lib.NVC_ERR_SHAPE
+    assert call(scale=-1.0) == _lib.NVC_ERR_SHAPE
+    assert call(batch=-1) == _lib.NVC_ERR_SHAPE
+    assert call(batch=1 << 31) == _lib.NVC_ERR_SHAPE
+    assert call(table=None) == _lib.NVC_ERR_NULL
+    assert call(pos_scene=None) == _lib.NVC_ERR_NULL
+    assert call(lights=None) == _lib.NVC_ERR_NULL
+    assert call(g_table=None) == _lib.NVC_ERR_NULL
+    assert call(spheres=None) == _lib.NVC_ERR_NULL                           # spheres given but no pointer
+    assert call(wsp=None) == _lib.NVC_ERR_WORKSPACE
+    assert call(wsb=255) == _lib.NVC_ERR_WORKSPACE
+    assert call(table=None, pos_scene=None, lights=None, spheres=None, g_table=None, wsp=None, batch=0) == 0
+    hdr = open(HEADER).read()
+    assert f"#define NVC_TRAIN_SHADOW_MAX_LIGHTS {_lib.NVC_TRAIN_SHADOW_MAX_LIGHTS}" in hdr
+    assert f"#define NVC_TRAIN_SHADOW_MAX_SPHERES {_lib.NVC_TRAIN_SHADOW_MAX_SPHERES}" in hdr
