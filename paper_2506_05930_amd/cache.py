@@ -211,17 +211,41 @@ class NVCache:
         return bufs
 
     def frame(self, pos_unit, pos_scene, nrm, lights, spheres, frame: int, batch: int, bufs: dict | None = None,
-              stream=None, ctr=None, side=None) -> dict:
+              stream=None, ctr=None, side=None, join: bool = True) -> dict:
         """Inference + WRS + neural DI on every pixel, and one training step.
 
         Without `side` everything runs in order on `stream`.  With a second
         stream `side`, the training pixels, labels and gradients run on it
         beside inference and WRS (they only read the parameters), and Adam
         runs on `stream` once both are done; the results are the same.
+
+        join=False (with `side`): the whole training step, Adam included, stays
+        on `side` and nothing joins at the end of the frame.  Inference waits
+        for the previous such frame's Adam, and Adam for this frame's
+        inference, the only two orderings between the halves; consecutive
+        frames then run without a cross-stream wait on the training side.
+        The parameters are still being updated on `side` when this returns:
+        another stream that reads them (inference outside a frame, a
+        checkpoint) first calls wait_training().
         """
         if bufs is None:
             n = pos_unit.shape[0]
             bufs = {"vis": torch.empty((n, self.mlp.n_out), dtype=self.vis_dtype, device=self.device)}
+        if side is not None and not join:
+            main = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.current_stream()
+            self.wait_training(main)
+            self.infer(pos_unit, bufs["vis"], stream=main)
+            inferred = torch.cuda.Event()
+            inferred.record(main)
+            bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"), stream=main,
+                                         ctr=ctr)
+            bufs["train"] = self.train_gradients(pos_unit, pos_scene, lights, spheres, frame, batch,
+                                                 bufs.get("train"), stream=side, ctr=ctr)
+            side.wait_event(inferred)
+            self.adam(side, ctr=ctr)
+            self._trained = torch.cuda.Event()
+            self._trained.record(side)
+            return bufs
         if side is None:
             self.infer(pos_unit, bufs["vis"], stream=stream)
             bufs["sample"] = self.sample(bufs["vis"], pos_scene, nrm, lights, frame, bufs.get("sample"),
@@ -240,13 +264,22 @@ class NVCache:
         self.adam(main, ctr=ctr)
         return bufs
 
+    def wait_training(self, stream=None):
+        """Make `stream` (default: the current one) wait for the training step left running by the last
+        frame(join=False); nothing to wait for otherwise."""
+        ev = getattr(self, "_trained", None)
+        if ev is not None:
+            (stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.current_stream()).wait_event(ev)
+
     # ------------------------------------------------------------ checkpoint
     def state_dict(self) -> dict:
+        self.wait_training()
         return {"table": self.table.detach().cpu(), "w": self.w.detach().cpu(),
                 "m_table": self.m_table.cpu(), "v_table": self.v_table.cpu(), "m_w": self.m_w.cpu(),
                 "v_w": self.v_w.cpu(), "step": self.step, "seed": self.seed}
 
     def load_state_dict(self, sd: dict):
+        self.wait_training()
         for k in ("table", "w", "m_table", "v_table", "m_w", "v_w"):
             getattr(self, k).copy_(sd[k].to(self.device))
         self.step = int(sd["step"])

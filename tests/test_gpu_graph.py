@@ -101,3 +101,39 @@ def test_frame_graph_replays_match_eager(scene):
         assert abs(ce.loss_buf.item() - cg.loss_buf.item()) <= 1e-5 * abs(ce.loss_buf.item())
         assert fe.ctr.cpu().tolist() == fgr.ctr.cpu().tolist() == [f + 1, f + 2]
         assert ce.step == cg.step == f + 1
+
+
+def test_pipelined_frames_match_joined_frames(scene):
+    """frame(join=False) leaves the training step with Adam on the second stream and never joins; four such
+    frames queued without a host synchronisation equal four joined frames: the same training pixels and
+    labels every frame, every output of the first frame, and afterwards what the order of the gradient
+    atomics allows (as for the graph replays)."""
+    wl = p1080()
+    p = params(wl)
+    batch = 4096
+    args = [t(scene[k]) for k in ("pos_unit", "pos", "nrm", "lights", "spheres")]
+    joined, piped = make_cache(wl, p), make_cache(wl, p)
+    side_j, side_p = torch.cuda.Stream(), torch.cuda.Stream()
+    out_j, out_p = [], []
+    for f in range(4):
+        out_j.append(joined.frame(*args, frame=f, batch=batch, side=side_j))
+        torch.cuda.synchronize()
+    for f in range(4):                                  # queued back to back
+        out_p.append(piped.frame(*args, frame=f, batch=batch, side=side_p, join=False))
+    piped.wait_training()
+    torch.cuda.synchronize()
+    assert joined.step == piped.step == 4
+    for f, (bj, bp) in enumerate(zip(out_j, out_p)):
+        assert torch.equal(bj["train"]["pix"], bp["train"]["pix"])
+        assert torch.equal(bj["train"]["labels"], bp["train"]["labels"])
+        if f == 0:
+            assert torch.equal(bj["vis"], bp["vis"])
+            for k in ("idx", "pmf", "wsum", "di"):
+                assert torch.equal(bj["sample"][k], bp["sample"][k])
+        else:
+            dv = (bj["vis"].float() - bp["vis"].float()).abs().max().item()
+            agree = (bj["sample"]["idx"] == bp["sample"]["idx"]).float().mean().item()
+            assert dv < 2e-3 and agree > 0.99, (f, dv, agree)
+    rel = ((joined.table - piped.table).norm() / joined.table.norm()).item()
+    assert rel < 1e-5, rel
+    assert abs(joined.loss_buf.item() - piped.loss_buf.item()) <= 1e-5 * abs(joined.loss_buf.item())

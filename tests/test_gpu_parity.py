@@ -265,6 +265,20 @@ def test_shadow_labels_large_batches_sampled(small_scene, batch, m):
     assert np.array_equal(lab.cpu().numpy()[sub], ref)
 
 
+@pytest.mark.parametrize("n_spheres", [1, 63, 1024, 1025, 4096])
+def test_shadow_labels_sphere_counts(n_spheres):
+    """Up to 1024 spheres the block shares its exact tests through a survivor list in LDS; above, each wave
+    tests its own survivors.  Both against the oracle, on a batch with a ragged last block."""
+    from paper_2506_05930_amd import api
+    sc = box_scene(0, 160, 90, 64, 8, n_spheres)
+    batch = 2 * 1024 + 333
+    pix = np.sort(philox.training_pixels(2, 5, batch, sc["pos"].shape[0]).astype(np.int32))
+    lab = torch.empty((batch, 8), dtype=torch.uint8, device=DEV)
+    api.nvc_shadow_labels(t(sc["pos"]), t(pix), t(sc["lights"]), t(sc["spheres"]), lab)
+    ref = shadow.labels_fp32(sc["pos"][pix], sc["lights"], sc["spheres"])
+    assert np.array_equal(lab.cpu().numpy(), ref)
+
+
 def test_shadow_labels_unit_cube_without_indirection():
     from paper_2506_05930_amd import api
     sc = unit_cube_scene(0, 4096, 8, 16, n_train=1024)
