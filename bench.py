@@ -9,10 +9,11 @@ A step runs every stage of the path on synthetic data resident in HBM:
   adam    Adam on 16.8M table + 12,288 MLP params, repack        (nvc_adam x2, nvc_pack_mlp)
 
 Prints one JSON line.  `value` is visibility queries/s (one query = one pixel
-against all 32 lights) over whole frames, training included.  In timed
-frames inference + WRS run on one stream and the training step (pixels,
-labels, gradients, Adam) on a second one, frame after frame: inference waits
-for the previous frame's Adam, Adam for this frame's inference.  The
+against all 32 lights) over whole frames, training included.  Timed frames
+run through FramePipeline: inference + WRS on one stream, the gradient pass
+and Adam on a second, and the next frame's training pixels and shadow labels
+on a third (they depend on the frame number and the scene only); inference
+waits for the previous frame's Adam, Adam for this frame's inference.  The
 per-stage times come from a separate pass that runs every stage in order on
 one stream.
 """
@@ -369,7 +370,7 @@ def main():
     import torch
 
     from paper_2506_05930_amd import api
-    from paper_2506_05930_amd.cache import NVCache
+    from paper_2506_05930_amd.cache import FramePipeline, NVCache
     from workloads import box_scene, get_workload, init_params
     from workloads.scenes import SCENE_EXTENT
 
@@ -410,9 +411,6 @@ def main():
         print(json.dumps(run_mlp(args, wl, cache, pos_unit, dev)))
         return
 
-    side = torch.cuda.Stream()
-    inf_done = torch.cuda.Event()
-    adam_done = torch.cuda.Event()
 
     def do_sample(frame, st=None):
         if clustered:
@@ -444,6 +442,7 @@ def main():
         cache.gradients(wunit, labels=wlab, batch=nw, stream=st)
 
     fused = args.fused_labels and not clustered
+    cache.fused_labels = fused
 
     def do_labels(frame, st=None):
         if fused:
@@ -460,33 +459,19 @@ def main():
         else:
             cache.gradients(pos_unit, labels=labels, pix=pix, batch=B, stream=st)
 
+    if nw:
+        cache.set_world_samples(nw, wl.world_box, SCENE_EXTENT)
+    pipe = FramePipeline(cache, pos_unit, pos, nrm, lights, spheres, B, main=stream)
+
     def step(frame, ev=None, kev=None):
-        """One frame.  Timed frames run inference + WRS on `stream` and the whole training step
-        (pixels, labels, gradients, Adam) on a second stream, frame after frame without joining:
-        inference waits for the previous frame's Adam and Adam for this frame's inference, the only
-        two orderings the frame needs (`kev`: events around the inference and WRS launches on their
-        stream).  With `ev` every stage runs in order on one stream between events (the per-stage
-        breakdown)."""
+        """One frame.  Timed frames go through FramePipeline: inference + WRS on `stream`, the gradient
+        pass and Adam on a second stream, the next frame's training pixels and labels on a third
+        (`kev`: events around the inference and WRS launches).  With `ev` every stage runs in order
+        on one stream between events (the per-stage breakdown)."""
         if ev is None:
-            stream.wait_event(adam_done)
-            if kev is not None:
-                kev[0].record(stream)
-            api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis, stream)
-            inf_done.record(stream)
-            if kev is not None:
-                kev[1].record(stream)
-            do_sample(frame, stream)
-            if kev is not None:
-                kev[2].record(stream)
-            api.nvc_select_pixels(cache.seed, frame, n_pix, pix, pix_ws, side)
-            do_labels(frame, side)
-            do_gradients(side)
-            do_world(frame, side)
-            side.wait_event(inf_done)
-            cache.adam(side)
-            adam_done.record(side)
+            pipe.run(frame, events=kev)
             return
-        stream.wait_stream(side)
+        pipe.finish()
         ev[0].record(stream)
         api.nvc_infer(cache.grid, cache.mlp, cache.table, cache.packed, pos_unit, vis)
         ev[1].record(stream)
@@ -514,7 +499,7 @@ def main():
     t_start.record(stream)
     for f in range(args.steps):
         step(args.warmup + f, kev=kevs[f])
-    stream.wait_stream(side)
+    pipe.finish()
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_per_step = t_start.elapsed_time(t_end) / args.steps
@@ -551,7 +536,7 @@ def main():
         r0.record(stream)
         for f in range(args.steps):
             step(f0 + args.warmup + f)
-        stream.wait_stream(side)
+        pipe.finish()
         r1.record(stream)
         torch.cuda.synchronize()
         rows_ms = r0.elapsed_time(r1) / args.steps
@@ -608,8 +593,8 @@ def main():
                    "labels": "inside the training kernel" if fused else "label kernel"},
         "ms_per_frame": ms_per_step,
         "ms_per_frame_rowmajor": None if rows_ms is None else round(rows_ms, 4),
-        "streams": "inference + WRS on one stream, the training step with Adam on a second (inference waits for "
-                   "the previous Adam, Adam for this inference); stage_ms from a serial pass",
+        "streams": "FramePipeline: inference + WRS, gradient pass + Adam, next frame's pixels + labels on three "
+                   "streams; stage_ms from a serial pass",
         "timed_launch_ms": {k: round(v, 4) for k, v in timed_ms.items()},
         "ms_per_frame_serial": None if stage_ms is None else round(sum(stage_ms.values()), 4),
         "stage_ms": None if stage_ms is None else {k: round(v, 4) for k, v in stage_ms.items()},

@@ -289,6 +289,124 @@ class NVCache:
         self.pack()
 
 
+class FramePipeline:
+    """Frames of a static scene queued on three streams, each frame's training pixels and shadow labels
+    prepared one frame ahead.
+
+    Frame f is the work of NVCache.frame: inference + WRS (+ DI) of every pixel, the training pixels
+    (and world-space points) with their shadow labels, the gradient pass and Adam.  The pixels and
+    labels of a frame depend only on the seed, the frame number and the scene, not on the parameters,
+    so they run on a third stream (`prep`) while the previous frame's gradient pass and Adam run on
+    `train`; inference + WRS run on `main`.  The orderings kept between the streams:
+      * inference of frame f after Adam of frame f - 1, Adam of frame f after inference of frame f;
+      * the gradient pass of frame f after the labels of frame f;
+      * the pixels of frame f + 2 after the gradient pass of frame f has read the pixel and label set
+        that they overwrite (two sets alternate).
+    Each frame computes what it computes when the frames run one after another; only the placement
+    in time across the streams changes.  run(f) already queues the labels of frame f + 1, so the scene
+    tensors must stay unchanged while frames are queued: call finish() before changing them, or
+    before reading the parameters on another stream.  `bufs` ("vis", "sample") hold the last frame's
+    outputs, ordered on `main`.  With the cache's fused labels the prep stream only picks the pixels.
+    """
+
+    def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, main=None):
+        dev = cache.device
+        self.cache = cache
+        self.args = (pos_unit, pos_scene, nrm, lights, spheres)
+        self.batch = int(batch)
+        self.main = main if isinstance(main, torch.cuda.Stream) else torch.cuda.current_stream(dev)
+        self.train = torch.cuda.Stream(device=dev)
+        self.prep = torch.cuda.Stream(device=dev)
+        n, m = pos_unit.shape[0], cache.mlp.n_out
+        self.bufs = {"vis": torch.empty((n, m), dtype=cache.vis_dtype, device=dev), "sample": None}
+        world = getattr(cache, "world", None)
+        self.n_world = world[0] if world is not None else 0
+        self.sets = []
+        for _ in range(2):
+            s = {"pix": torch.empty(self.batch, dtype=torch.int32, device=dev),
+                 "labels": torch.empty((self.batch, m), dtype=torch.uint8, device=dev)}
+            if self.n_world:
+                s["wpos"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
+                s["wunit"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
+                s["wlabels"] = torch.empty((self.n_world, m), dtype=torch.uint8, device=dev)
+            self.sets.append(s)
+        self.labelled = [torch.cuda.Event(), torch.cuda.Event()]
+        self.consumed = [torch.cuda.Event(), torch.cuda.Event()]
+        self.inferred = torch.cuda.Event()
+        self.trained = torch.cuda.Event()
+        self.pix_ws = cache.pixel_workspace(n)
+        cache._ensure_workspace(max(self.batch, self.n_world))
+        self._queued = None                    # frame whose pixels and labels are queued on `prep`
+
+    def _labels(self, pos, pix, out, frame):
+        c = self.cache
+        lights, spheres = self.args[3], self.args[4]
+        if c.clustered:
+            api.nvc_shadow_labels_clustered(pos, pix, lights, c.cl_offsets, c.cl_members, spheres, c.seed, frame,
+                                            out, self.prep)
+        else:
+            api.nvc_shadow_labels(pos, pix, lights, spheres, out, self.prep)
+
+    def _prepare(self, frame: int):
+        c, s, k = self.cache, self.sets[frame % 2], frame % 2
+        pos_unit, pos_scene = self.args[0], self.args[1]
+        self.prep.wait_event(self.consumed[k])
+        api.nvc_select_pixels(c.seed, frame, pos_unit.shape[0], s["pix"], self.pix_ws, self.prep)
+        fused = c.fused_labels and not c.clustered
+        if not fused:
+            self._labels(pos_scene, s["pix"], s["labels"], frame)
+        if self.n_world:
+            _, box, extent = c.world
+            api.nvc_world_samples(c.seed, frame, box, extent, s["wpos"], s["wunit"], self.prep)
+            if not fused:
+                self._labels(s["wpos"], None, s["wlabels"], frame)
+        self.labelled[k].record(self.prep)
+        self._queued = frame
+
+    def run(self, frame: int, events=None) -> dict:
+        """Queue frame `frame` (and the pixels and labels of frame + 1).  events: optional three timing
+        events recorded on `main` before inference, after inference and after WRS."""
+        c = self.cache
+        pos_unit, pos_scene, nrm, lights, spheres = self.args
+        if self._queued != frame:
+            self._prepare(frame)
+        self.main.wait_event(self.trained)
+        if events is not None:
+            events[0].record(self.main)
+        c.infer(pos_unit, self.bufs["vis"], stream=self.main)
+        self.inferred.record(self.main)
+        if events is not None:
+            events[1].record(self.main)
+        self.bufs["sample"] = c.sample(self.bufs["vis"], pos_scene, nrm, lights, frame, self.bufs["sample"],
+                                       stream=self.main)
+        if events is not None:
+            events[2].record(self.main)
+        k, s = frame % 2, self.sets[frame % 2]
+        self.train.wait_event(self.labelled[k])
+        fused = c.fused_labels and not c.clustered
+        if fused:
+            c.gradients_shadow(pos_unit, pos_scene, lights, spheres, pix=s["pix"], batch=self.batch,
+                               stream=self.train)
+            if self.n_world:
+                c.gradients_shadow(s["wunit"], s["wpos"], lights, spheres, batch=self.n_world, stream=self.train)
+        else:
+            c.gradients(pos_unit, labels=s["labels"], pix=s["pix"], batch=self.batch, stream=self.train)
+            if self.n_world:
+                c.gradients(s["wunit"], labels=s["wlabels"], batch=self.n_world, stream=self.train)
+        self.consumed[k].record(self.train)
+        self.train.wait_event(self.inferred)
+        c.adam(self.train)
+        self.trained.record(self.train)
+        c._trained = self.trained
+        self._prepare(frame + 1)
+        return self.bufs
+
+    def finish(self):
+        """`main` waits for everything queued (the labels prepared ahead included)."""
+        self.main.wait_stream(self.train)
+        self.main.wait_stream(self.prep)
+
+
 class FrameGraph:
     """One frame of the cache recorded once into a HIP graph and replayed.
 
