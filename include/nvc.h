@@ -372,6 +372,36 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                    float* g_table, float* g_w, float* loss_out,
                    void* workspace, int64_t workspace_bytes, void* stream);
 
+/* The routing plan of nvc_train_step's table scatter, computed on its own
+ * (Sec. 3.3: the gradient of every corner of every sample's cell goes to the
+ * table).  For each training block and each partition of the table (2^k
+ * consecutive entries of a level) the plan holds how many records the block's
+ * samples write there and where, and the chunk table of the partition sums.
+ * It depends only on the positions pos[pix[b]] (as for nvc_train_step), the
+ * batch and the grid, not on the parameters, so it can be computed ahead of
+ * the gradient pass, beside other work, into a buffer of
+ * nvc_train_plan_bytes bytes (0: this batch trains through direct atomics
+ * and needs no plan; nvc_train_plan then does nothing).  Errors as
+ * nvc_train_step; NVC_ERR_WORKSPACE if plan is NULL or too small.  Device
+ * pointers; the plan is owned by the caller. */
+int64_t nvc_train_plan_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch);
+int nvc_train_plan(const nvc_grid* grid, const nvc_mlp* mlp, const float* pos, const int32_t* pix, int64_t batch,
+                   void* plan, int64_t plan_bytes, void* stream);
+
+/* nvc_train_step with the routing plan from nvc_train_plan instead of its own
+ * (the same pos, pix and batch; the plan must be complete when this pass runs,
+ * e.g. computed earlier on the same stream or behind an event).  Given the
+ * plan of the same samples the gradients are those of nvc_train_step.  A plan
+ * of other samples gives wrong gradients but no access outside the buffers:
+ * the kernels bound every record index by the batch's record count.  plan and
+ * plan_bytes as for nvc_train_plan (ignored when that size is 0); everything
+ * else as nvc_train_step. */
+int nvc_train_step_planned(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
+                           const float* pos, const int32_t* pix, int64_t batch, const uint8_t* labels,
+                           const float* dvis, int32_t loss, float grad_scale, float* g_table, float* g_w,
+                           float* loss_out, const void* plan, int64_t plan_bytes, void* workspace,
+                           int64_t workspace_bytes, void* stream);
+
 /* nvc_train_step in labelled mode with the shadow labels computed inside the
  * training kernel instead of read from memory (Sec. 3.4: each training example
  * pairs a position with the visibility of every light, from one shadow ray per

@@ -33,7 +33,8 @@ EXPORTS = [
     "nvc_train_workspace_bytes", "nvc_train_step", "nvc_adam", "nvc_counters_advance",
     "nvc_cluster_lights", "nvc_shadow_labels_clustered", "nvc_sample_clustered", "nvc_world_samples",
     "nvc_graph_begin", "nvc_graph_end", "nvc_graph_launch", "nvc_graph_destroy", "nvc_select_pixels_noalloc",
-    "nvc_forward_f64", "nvc_train_step_shadow",
+    "nvc_forward_f64", "nvc_train_step_shadow", "nvc_train_plan_bytes", "nvc_train_plan",
+    "nvc_train_step_planned",
 ]
 
 
@@ -77,6 +78,12 @@ _SIGS = {
     "nvc_train_step": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p, c_int64,
                                  c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int64, c_void_p]),
+    "nvc_train_plan_bytes": (c_int64, [POINTER(NvcGrid), POINTER(NvcMlp), c_int64]),
+    "nvc_train_plan": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_int64, c_void_p, c_int64,
+                                 c_void_p]),
+    "nvc_train_step_planned": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_int64, c_void_p, c_void_p, c_int32, c_float, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_int64, c_void_p, c_int64, c_void_p]),
     "nvc_train_step_shadow": (c_int32, [POINTER(NvcGrid), POINTER(NvcMlp), c_void_p, c_void_p, c_void_p, c_void_p,
                                         c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_int32, c_int32, c_float,
                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p]),

@@ -391,6 +391,48 @@ def nvc_train_step(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torc
                                                             pw, po, pws, wsb, _stream(stream)))
 
 
+def nvc_train_plan_bytes(grid: NvcGrid, mlp: NvcMlp, batch: int) -> int:
+    return _lib.check("nvc_train_plan_bytes", _lib.load().nvc_train_plan_bytes(ctypes.byref(grid), ctypes.byref(mlp),
+                                                                               int(batch)))
+
+
+def nvc_train_plan(grid: NvcGrid, mlp: NvcMlp, pos: torch.Tensor, pix, batch: int, plan: torch.Tensor,
+                   stream=None) -> None:
+    """The routing plan of the table scatter for these samples (see nvc_train_step_planned)."""
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    px = _ptr(pix, "pix", torch.int32, (batch,), optional=True)
+    if pix is None and pos.shape[0] < batch:
+        raise ValueError("pos has fewer rows than the batch")
+    pl = _ptr(plan, "plan")
+    _lib.check("nvc_train_plan", _lib.load().nvc_train_plan(ctypes.byref(grid), ctypes.byref(mlp), pp, px, int(batch),
+                                                            pl, plan.numel() * plan.element_size(), _stream(stream)))
+
+
+def nvc_train_step_planned(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor,
+                           pos: torch.Tensor, pix, batch: int, labels, dvis, loss: int, grad_scale: float,
+                           g_table: torch.Tensor, g_w: torch.Tensor, loss_out, plan: torch.Tensor,
+                           workspace: torch.Tensor, stream=None) -> None:
+    tshape = (grid.n_levels, 1 << grid.log2_T, grid.n_feat)
+    pt = _ptr(table, "table", torch.float32, tshape)
+    pk = _ptr(packed, "packed")
+    pp = _ptr(pos, "pos", torch.float32, (None, 3))
+    px = _ptr(pix, "pix", torch.int32, (batch,), optional=True)
+    if pix is None and pos.shape[0] < batch:
+        raise ValueError("pos has fewer rows than the batch")
+    pl = _ptr(labels, "labels", torch.uint8, (batch, mlp.n_out), optional=True)
+    pd = _ptr(dvis, "dvis", torch.float32, (batch, mlp.n_out), optional=True)
+    pg = _ptr(g_table, "g_table", torch.float32, tshape)
+    pw = _ptr(g_w, "g_w", torch.float32, (nvc_mlp_param_count(mlp),))
+    po = _ptr(loss_out, "loss_out", torch.float32, (1,), optional=True)
+    ppl = _ptr(plan, "plan")
+    pws = _ptr(workspace, "workspace")
+    _lib.check("nvc_train_step_planned",
+               _lib.load().nvc_train_step_planned(ctypes.byref(grid), ctypes.byref(mlp), pt, pk, pp, px, int(batch), pl,
+                                                  pd, int(loss), float(grad_scale), pg, pw, po, ppl,
+                                                  plan.numel() * plan.element_size(), pws,
+                                                  workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def nvc_train_step_shadow(grid: NvcGrid, mlp: NvcMlp, table: torch.Tensor, packed: torch.Tensor, pos: torch.Tensor,
                           pos_scene: torch.Tensor, pix, batch: int, lights: torch.Tensor, spheres: torch.Tensor,
                           loss: int, grad_scale: float, g_table: torch.Tensor, g_w: torch.Tensor, loss_out,

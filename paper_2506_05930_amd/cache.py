@@ -137,14 +137,31 @@ class NVCache:
 
     # ------------------------------------------------------------ training
     def gradients(self, pos_unit, labels=None, dvis=None, pix=None, batch: int | None = None,
-                  grad_scale: float = 0.0, stream=None):
-        """Accumulate the gradients of one batch into g_table / g_w (and the loss into loss_buf)."""
+                  grad_scale: float = 0.0, stream=None, plan=None):
+        """Accumulate the gradients of one batch into g_table / g_w (and the loss into loss_buf).  plan: the
+        routing plan of these samples from plan() (computed ahead), else the pass computes its own."""
         if batch is None:
             batch = pix.shape[0] if pix is not None else pos_unit.shape[0]
         self._ensure_workspace(batch)
+        loss_out = self.loss_buf if labels is not None else None
+        if plan is not None:
+            api.nvc_train_step_planned(self.grid, self.mlp, self.table, self.packed, pos_unit, pix, batch, labels,
+                                       dvis, self.loss, grad_scale, self.g_table, self.g_w, loss_out, plan,
+                                       self.workspace, stream)
+            return
         api.nvc_train_step(self.grid, self.mlp, self.table, self.packed, pos_unit, pix, batch, labels, dvis,
-                           self.loss, grad_scale, self.g_table, self.g_w, self.loss_buf if labels is not None else None,
-                           self.workspace, stream)
+                           self.loss, grad_scale, self.g_table, self.g_w, loss_out, self.workspace, stream)
+
+    def new_plan(self, batch: int) -> torch.Tensor:
+        """A buffer for the routing plan of a batch of this size."""
+        return torch.empty(max(api.nvc_train_plan_bytes(self.grid, self.mlp, batch), 256), dtype=torch.uint8,
+                           device=self.device)
+
+    def plan(self, pos_unit, pix, batch: int, plan: torch.Tensor, stream=None) -> torch.Tensor:
+        """The routing plan of the table scatter for these samples, for gradients(plan=...): it depends on
+        the positions only, so it can be computed ahead of the gradient pass on another stream."""
+        api.nvc_train_plan(self.grid, self.mlp, pos_unit, pix, batch, plan, stream)
+        return plan
 
     def gradients_shadow(self, pos_unit, pos_scene, lights, spheres, pix=None, batch: int | None = None,
                          grad_scale: float = 0.0, labels_out=None, stream=None):
@@ -302,6 +319,8 @@ class FramePipeline:
       * the gradient pass of frame f after the labels of frame f;
       * the pixels of frame f + 2 after the gradient pass of frame f has read the pixel and label set
         that they overwrite (two sets alternate).
+    The routing plan of each frame's table scatter (a function of the pixels' positions only) is
+    computed on `prep` too, into the set's own plan buffer.
     Each frame computes what it computes when the frames run one after another; only the placement
     in time across the streams changes.  run(f) already queues the labels of frame f + 1, so the scene
     tensors must stay unchanged while frames are queued: call finish() before changing them, or
@@ -324,7 +343,8 @@ class FramePipeline:
         self.sets = []
         for _ in range(2):
             s = {"pix": torch.empty(self.batch, dtype=torch.int32, device=dev),
-                 "labels": torch.empty((self.batch, m), dtype=torch.uint8, device=dev)}
+                 "labels": torch.empty((self.batch, m), dtype=torch.uint8, device=dev),
+                 "plan": cache.new_plan(self.batch)}
             if self.n_world:
                 s["wpos"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
                 s["wunit"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
@@ -353,6 +373,8 @@ class FramePipeline:
         self.prep.wait_event(self.consumed[k])
         api.nvc_select_pixels(c.seed, frame, pos_unit.shape[0], s["pix"], self.pix_ws, self.prep)
         fused = c.fused_labels and not c.clustered
+        if not fused:
+            c.plan(pos_unit, s["pix"], self.batch, s["plan"], stream=self.prep)
         if not fused:
             self._labels(pos_scene, s["pix"], s["labels"], frame)
         if self.n_world:
@@ -390,7 +412,8 @@ class FramePipeline:
             if self.n_world:
                 c.gradients_shadow(s["wunit"], s["wpos"], lights, spheres, batch=self.n_world, stream=self.train)
         else:
-            c.gradients(pos_unit, labels=s["labels"], pix=s["pix"], batch=self.batch, stream=self.train)
+            c.gradients(pos_unit, labels=s["labels"], pix=s["pix"], batch=self.batch, stream=self.train,
+                        plan=s["plan"])
             if self.n_world:
                 c.gradients(s["wunit"], labels=s["wlabels"], batch=self.n_world, stream=self.train)
         self.consumed[k].record(self.train)

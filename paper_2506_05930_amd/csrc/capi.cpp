@@ -296,6 +296,59 @@ int nvc_train_step(const nvc_grid* grid, const nvc_mlp* mlp, const float* table,
                                    g_w, loss_out, workspace, (hipStream_t)stream));
 }
 
+int64_t nvc_train_plan_bytes(const nvc_grid* grid, const nvc_mlp* mlp, int64_t batch) {
+    GridHost g{};
+    NetShape s{};
+    const int st = check_net(grid, mlp, &g, &s);
+    if (st) return st;
+    if (batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
+    if (!train_supported(g, s)) return NVC_ERR_UNSUPPORTED;
+    if (batch == 0) return 0;
+    return train_plan_bytes(g, s, batch);
+}
+
+int nvc_train_plan(const nvc_grid* grid, const nvc_mlp* mlp, const float* pos, const int32_t* pix, int64_t batch,
+                   void* plan, int64_t plan_bytes, void* stream) {
+    GridHost g{};
+    NetShape s{};
+    const int st = check_net(grid, mlp, &g, &s);
+    if (st) return st;
+    if (batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
+    if (!train_supported(g, s)) return NVC_ERR_UNSUPPORTED;
+    if (batch == 0) return NVC_OK;
+    const int64_t need = train_plan_bytes(g, s, batch);
+    if (need == 0) return NVC_OK;
+    if (!pos) return NVC_ERR_NULL;
+    if (!plan || plan_bytes < need) return NVC_ERR_WORKSPACE;
+    return hip_status(launch_train_plan(g, s, pos, pix, batch, plan, (hipStream_t)stream));
+}
+
+int nvc_train_step_planned(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
+                           const float* pos, const int32_t* pix, int64_t batch, const uint8_t* labels,
+                           const float* dvis, int32_t loss, float grad_scale, float* g_table, float* g_w,
+                           float* loss_out, const void* plan, int64_t plan_bytes, void* workspace,
+                           int64_t workspace_bytes, void* stream) {
+    GridHost g{};
+    NetShape s{};
+    const int st = check_net(grid, mlp, &g, &s);
+    if (st) return st;
+    if (batch < 0 || batch >= ((int64_t)1 << 31)) return NVC_ERR_SHAPE;
+    if (loss != NVC_LOSS_BCE && loss != NVC_LOSS_L2) return NVC_ERR_SHAPE;
+    if (!(grad_scale >= 0.0f) || !isfinite(grad_scale)) return NVC_ERR_SHAPE;
+    if ((labels == nullptr) == (dvis == nullptr)) return labels ? NVC_ERR_SHAPE : NVC_ERR_NULL;
+    if (!train_supported(g, s)) return NVC_ERR_UNSUPPORTED;
+    if (batch == 0) return NVC_OK;
+    if (!table || !packed || !pos || !g_table || !g_w) return NVC_ERR_NULL;
+    const int64_t need = train_workspace_bytes(g, s, batch);
+    if (!workspace || workspace_bytes < need) return NVC_ERR_WORKSPACE;
+    const int64_t pneed = train_plan_bytes(g, s, batch);
+    if (pneed > 0 && (!plan || plan_bytes < pneed)) return NVC_ERR_WORKSPACE;
+    const PackPlan p = make_pack_plan(s);
+    return hip_status(launch_train_planned(g, s, p, table, packed, pos, pix, batch, labels, dvis, loss, grad_scale,
+                                           g_table, g_w, loss_out, pneed > 0 ? plan : nullptr, workspace,
+                                           (hipStream_t)stream));
+}
+
 int nvc_train_step_shadow(const nvc_grid* grid, const nvc_mlp* mlp, const float* table, const void* packed,
                           const float* pos, const float* pos_scene, const int32_t* pix, int64_t batch,
                           const float* lights, int32_t m, const float* spheres, int32_t n_spheres, int32_t loss,

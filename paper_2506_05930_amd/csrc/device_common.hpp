@@ -441,7 +441,14 @@ __device__ inline void wrs_weight(const float4& l, float px, float py, float pz,
     const float d2 = fmaxf((dx * dx + dy * dy) + dz * dz, 1e-6f);
     if (has_n) {
         const float nd = (nx * dx + ny * dy) + nz * dz;
-        f = __fdiv_rn(l.w * fmaxf(nd, 0.0f), d2 * sqrt_rn(d2));
+        // max(nd, 0) = 0 (nd <= 0, or NaN): the denominator is positive (d2 >= 1e-6), so the quotient is
+        // the numerator l.w * 0 itself (a zero, or NaN for a non-finite intensity), and the division and
+        // the root are skipped; a wave skips them whenever none of its pixels faces the light.  (The sign
+        // of such a zero never reaches an output: the sums start at +0 and a picked light has w > 0.)
+        if (nd > 0.0f)
+            f = __fdiv_rn(l.w * nd, d2 * sqrt_rn(d2));
+        else
+            f = l.w * 0.0f;
     } else {
         f = __fdiv_rn(l.w, d2);
     }

@@ -97,6 +97,15 @@ hipError_t launch_train(const GridHost& g, const NetShape& s, const PackPlan& pl
                         const void* packed, const float* pos, const int32_t* pix, int64_t batch,
                         const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
                         float* g_w, float* loss_out, void* workspace, hipStream_t st);
+// The routing plan of the table scatter computed ahead (for the same samples and batch), and the
+// training pass that uses it instead of computing its own.
+int64_t train_plan_bytes(const GridHost& g, const NetShape& s, int64_t batch);
+hipError_t launch_train_plan(const GridHost& g, const NetShape& s, const float* pos, const int32_t* pix,
+                             int64_t batch, void* plan, hipStream_t st);
+hipError_t launch_train_planned(const GridHost& g, const NetShape& s, const PackPlan& plan, const float* table,
+                                const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                                const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
+                                float* g_w, float* loss_out, const void* route_plan, void* workspace, hipStream_t st);
 // Shadow-label inputs of the training pass that computes its labels in the kernel.
 struct ShadowArgs {
     const float* pos_scene;   // [*][3] scene units, indexed like the unit-cube positions

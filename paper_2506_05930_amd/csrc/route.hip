@@ -175,6 +175,8 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     const int b = (int)r.chunk_bucket[c];
+    // A plan computed for other samples gives wrong sums, never accesses outside the buffers.
+    if (b < 0 || b >= r.nb) return;
     int l = 0;
     while (l + 1 < n_levels && r.bucket_off[l + 1] <= b) ++l;
     const uint32_t ps = 1u << r.k;
@@ -183,7 +185,7 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
     const uint32_t q = c - r.chunk_base[b];
     const bool shared = r.chunk_base[b + 1] - r.chunk_base[b] > 1;
     const uint32_t r0 = r.base[b] + q * (uint32_t)kRouteChunk;
-    const uint32_t r1 = min(r.base[b + 1], r0 + (uint32_t)kRouteChunk);
+    const uint32_t r1 = max(r0, min(min(r.base[b + 1], r0 + (uint32_t)kRouteChunk), r.cap));
     for (uint32_t i = threadIdx.x; i < ps * F; i += blockDim.x) part[i] = 0ull;
     __syncthreads();
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
@@ -223,7 +225,7 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
 #pragma unroll
         for (int j = 0; j < 2 * F; ++j) acc[j] = to_fixed(w[0][j], scale);
         auto flush = [&]() {
-            const uint32_t lo0 = kc & 0xFFFFu, lo1 = kc >> 16;
+            const uint32_t lo0 = kc & (ps - 1u), lo1 = (kc >> 16) & (ps - 1u);   // < 2^k for every real key
 #pragma unroll
             for (int j = 0; j < F; ++j) {
                 if (acc[j] != 0) atomicAdd(&part[lo0 * F + j], (unsigned long long)acc[j]);

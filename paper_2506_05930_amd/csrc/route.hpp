@@ -58,6 +58,7 @@ struct RouteDev {
     float* vals;                              // [R][2F]: values of entry e0, then of e1
     uint32_t* keys;                           // [R]: (e0 & M) | (e1 & M) << 16, M = 2^k - 1
     float* rec_max;                           // [G]: largest |value| each training block wrote
+    uint32_t cap;                             // records the buffers hold (batch * n_levels * 4)
 };
 
 // Fixed-point scale 2^S for the partition sums, from the largest record

@@ -574,7 +574,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHADOW ? 2 
                             const int bkt = a.route.bucket_off[l] + (int)(e0 >> a.route.k);
                             const uint32_t end = a.route.base[bkt + 1];
                             const uint32_t slot = atomicAdd(&cursor[bkt], 1u);
-                            if (slot < end) {
+                            if (slot < end && slot < a.route.cap) {
                                 float* dst = a.route.vals + (size_t)slot * (2 * C::F);
 #pragma unroll
                                 for (int j = 0; j < 2 * C::F; ++j) rec_max = fmaxf(rec_max, fabsf(v[j]));
@@ -773,6 +773,32 @@ static WsLayout ws_layout(const GridHost& g, int64_t n_w, int64_t batch, int G, 
     return L;
 }
 
+// Routing plan (nvc_train_plan): the plan arrays of the workspace layout, in a buffer of their own
+// (each part 256-byte aligned): [nb][G] offsets | [nb] totals | [nb+1] bases | [nb+1] chunk bases |
+// [R / chunk + nb] chunk buckets.
+struct PlanLayout {
+    int64_t offsets, totals, base, chunk_base, chunk_bucket, total;
+};
+
+static PlanLayout plan_layout(const GridHost& g, int64_t batch, int G, const RoutePlan& rp) {
+    PlanLayout L{};
+    if (!rp.ok) return L;
+    const int64_t R = batch * g.n_levels * 4;
+    int64_t o = 0;
+    L.offsets = o;
+    o = align256(o + (int64_t)G * rp.nb * 4);
+    L.totals = o;
+    o = align256(o + (int64_t)rp.nb * 4);
+    L.base = o;
+    o = align256(o + (int64_t)(rp.nb + 1) * 4);
+    L.chunk_base = o;
+    o = align256(o + (int64_t)(rp.nb + 1) * 4);
+    L.chunk_bucket = o;
+    o = align256(o + ((R + kRouteChunk - 1) / kRouteChunk + rp.nb) * 4);
+    L.total = o;
+    return L;
+}
+
 static int64_t n_weights(const NetShape& s) {
     return (int64_t)s.n_in * s.width + (int64_t)(s.n_hidden - 1) * s.width * s.width + (int64_t)s.width * s.n_out;
 }
@@ -799,7 +825,7 @@ static hipError_t launch_train_impl(const GridHost& gh, const NetShape& s, const
                                     const void* packed, const float* pos, const int32_t* pix, int64_t batch,
                                     const uint8_t* labels, const float* dvis, int loss, float grad_scale,
                                     float* g_table, float* g_w, float* loss_out, void* workspace,
-                                    const ShadowArgs* sh, hipStream_t st) {
+                                    const ShadowArgs* sh, const void* plan_buf, hipStream_t st) {
     TrainArgs a{};
     a.g = grid_to_dev(gh);
     a.table = table;
@@ -857,17 +883,31 @@ static hipError_t launch_train_impl(const GridHost& gh, const NetShape& s, const
         r.nb = rp.nb;
         for (int l = 0; l <= kMaxLevels; ++l) r.bucket_off[l] = l <= gh.n_levels ? rp.bucket_off[l] : rp.nb;
         for (int l = 0; l < kMaxLevels; ++l) r.entries[l] = rp.entries[l];
-        r.offsets = reinterpret_cast<uint32_t*>(ws + wl.offsets);
-        r.totals = reinterpret_cast<uint32_t*>(ws + wl.totals);
-        r.base = reinterpret_cast<uint32_t*>(ws + wl.base);
-        r.chunk_base = reinterpret_cast<uint32_t*>(ws + wl.chunk_base);
-        r.chunk_bucket = reinterpret_cast<uint32_t*>(ws + wl.chunk_bucket);
+        if (plan_buf) {
+            // the plan was computed beforehand (nvc_train_plan) from the same samples
+            const PlanLayout pl = plan_layout(gh, batch, G, rp);
+            unsigned char* pb = reinterpret_cast<unsigned char*>(const_cast<void*>(plan_buf));
+            r.offsets = reinterpret_cast<uint32_t*>(pb + pl.offsets);
+            r.totals = reinterpret_cast<uint32_t*>(pb + pl.totals);
+            r.base = reinterpret_cast<uint32_t*>(pb + pl.base);
+            r.chunk_base = reinterpret_cast<uint32_t*>(pb + pl.chunk_base);
+            r.chunk_bucket = reinterpret_cast<uint32_t*>(pb + pl.chunk_bucket);
+        } else {
+            r.offsets = reinterpret_cast<uint32_t*>(ws + wl.offsets);
+            r.totals = reinterpret_cast<uint32_t*>(ws + wl.totals);
+            r.base = reinterpret_cast<uint32_t*>(ws + wl.base);
+            r.chunk_base = reinterpret_cast<uint32_t*>(ws + wl.chunk_base);
+            r.chunk_bucket = reinterpret_cast<uint32_t*>(ws + wl.chunk_bucket);
+        }
         r.vals = reinterpret_cast<float*>(ws + wl.vals);
         r.keys = reinterpret_cast<uint32_t*>(ws + wl.keys);
         r.rec_max = reinterpret_cast<float*>(ws + wl.rec_max);
-        err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
-        if (err == hipSuccess) err = launch_route_prefix(r, G, st);
-        if (err != hipSuccess) return err;
+        r.cap = (uint32_t)(batch * gh.n_levels * 4);
+        if (!plan_buf) {
+            err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
+            if (err == hipSuccess) err = launch_route_prefix(r, G, st);
+            if (err != hipSuccess) return err;
+        }
     }
     err = hipErrorNotSupported;
     dispatch_config(gh.n_feat, s, [&]<class C>() {
@@ -898,7 +938,44 @@ hipError_t launch_train(const GridHost& gh, const NetShape& s, const PackPlan& p
                         const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
                         float* g_w, float* loss_out, void* workspace, hipStream_t st) {
     return launch_train_impl(gh, s, plan, table, packed, pos, pix, batch, labels, dvis, loss, grad_scale, g_table, g_w,
-                             loss_out, workspace, nullptr, st);
+                             loss_out, workspace, nullptr, nullptr, st);
+}
+
+hipError_t launch_train_planned(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
+                                const void* packed, const float* pos, const int32_t* pix, int64_t batch,
+                                const uint8_t* labels, const float* dvis, int loss, float grad_scale, float* g_table,
+                                float* g_w, float* loss_out, const void* route_plan, void* workspace, hipStream_t st) {
+    return launch_train_impl(gh, s, plan, table, packed, pos, pix, batch, labels, dvis, loss, grad_scale, g_table, g_w,
+                             loss_out, workspace, nullptr, route_plan, st);
+}
+
+int64_t train_plan_bytes(const GridHost& g, const NetShape& s, int64_t batch) {
+    const RoutePlan rp = train_route_plan(g, s, batch);
+    return plan_layout(g, batch, train_grid(g, s, batch, route_cursor_bytes(rp)), rp).total;
+}
+
+hipError_t launch_train_plan(const GridHost& gh, const NetShape& s, const float* pos, const int32_t* pix,
+                             int64_t batch, void* plan_buf, hipStream_t st) {
+    const RoutePlan rp = train_route_plan(gh, s, batch);
+    if (!rp.ok) return hipSuccess;                         // direct atomics: nothing to plan
+    const int G = train_grid(gh, s, batch, route_cursor_bytes(rp));
+    const PlanLayout pl = plan_layout(gh, batch, G, rp);
+    unsigned char* pb = reinterpret_cast<unsigned char*>(plan_buf);
+    RouteDev r{};
+    r.enabled = 1;
+    r.k = rp.k;
+    r.nb = rp.nb;
+    for (int l = 0; l <= kMaxLevels; ++l) r.bucket_off[l] = l <= gh.n_levels ? rp.bucket_off[l] : rp.nb;
+    for (int l = 0; l < kMaxLevels; ++l) r.entries[l] = rp.entries[l];
+    r.offsets = reinterpret_cast<uint32_t*>(pb + pl.offsets);
+    r.totals = reinterpret_cast<uint32_t*>(pb + pl.totals);
+    r.base = reinterpret_cast<uint32_t*>(pb + pl.base);
+    r.chunk_base = reinterpret_cast<uint32_t*>(pb + pl.chunk_base);
+    r.chunk_bucket = reinterpret_cast<uint32_t*>(pb + pl.chunk_bucket);
+    r.cap = (uint32_t)(batch * gh.n_levels * 4);
+    hipError_t err = launch_route_count(gh, r, pos, pix, batch, G, kTrainPts, st);
+    if (err == hipSuccess) err = launch_route_prefix(r, G, st);
+    return err;
 }
 
 hipError_t launch_train_shadow(const GridHost& gh, const NetShape& s, const PackPlan& plan, const float* table,
@@ -906,7 +983,7 @@ hipError_t launch_train_shadow(const GridHost& gh, const NetShape& s, const Pack
                                const ShadowArgs& sh, int loss, float grad_scale, float* g_table, float* g_w,
                                float* loss_out, void* workspace, hipStream_t st) {
     return launch_train_impl(gh, s, plan, table, packed, pos, pix, batch, nullptr, nullptr, loss, grad_scale, g_table,
-                             g_w, loss_out, workspace, &sh, st);
+                             g_w, loss_out, workspace, &sh, nullptr, st);
 }
 
 }  // namespace nvc

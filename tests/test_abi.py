@@ -346,3 +346,41 @@ def test_train_step_shadow_validates_before_launching(lib):
     hdr = open(HEADER).read()
     assert f"#define NVC_TRAIN_SHADOW_MAX_LIGHTS {_lib.NVC_TRAIN_SHADOW_MAX_LIGHTS}" in hdr
     assert f"#define NVC_TRAIN_SHADOW_MAX_SPHERES {_lib.NVC_TRAIN_SHADOW_MAX_SPHERES}" in hdr
+
+
+def test_train_plan_validates_before_launching(lib):
+    """The routing plan computed ahead: its size is the plan part of the training workspace (0 when the
+    batch trains through direct atomics); plan and planned step reject bad arguments before launching."""
+    gg, mm = ctypes.byref(g()), ctypes.byref(m())
+    P = ctypes.c_void_p(16)
+    N = None
+    b = 1 << 18
+    pb = lib.nvc_train_plan_bytes(gg, mm, b)
+    ws = lib.nvc_train_workspace_bytes(gg, mm, b)
+    assert 0 < pb < ws
+    assert lib.nvc_train_plan_bytes(gg, mm, 0) == 0
+    assert lib.nvc_train_plan_bytes(gg, mm, -1) == _lib.NVC_ERR_SHAPE
+    assert lib.nvc_train_plan_bytes(gg, mm, 1 << 26) == 0                  # direct atomics: no plan
+    assert lib.nvc_train_plan_bytes(None, mm, b) == _lib.NVC_ERR_NULL
+    f = lib.nvc_train_plan
+    assert f(gg, mm, None, N, b, P, pb, N) == _lib.NVC_ERR_NULL
+    assert f(gg, mm, P, N, b, None, pb, N) == _lib.NVC_ERR_WORKSPACE
+    assert f(gg, mm, P, N, b, P, pb - 1, N) == _lib.NVC_ERR_WORKSPACE
+    assert f(gg, mm, P, N, -3, P, pb, N) == _lib.NVC_ERR_SHAPE
+    assert f(None, None, None, N, 0, None, 0, N) == _lib.NVC_ERR_NULL
+    assert f(gg, mm, None, N, 0, None, 0, N) == 0                          # empty batch: nothing to do
+    assert f(gg, mm, None, N, 1 << 26, None, 0, N) == 0                    # nothing to plan
+    s = lib.nvc_train_step_planned
+
+    def call(labels=P, dvis=N, loss=0, scale=0.0, plan=P, plan_bytes=pb, wsp=P, wsb=ws, batch=b, table=P):
+        return s(gg, mm, table, P, P, N, batch, labels, dvis, loss, scale, P, P, N, plan, plan_bytes, wsp, wsb, N)
+
+    assert call(labels=N) == _lib.NVC_ERR_NULL                             # neither labels nor dvis
+    assert call(dvis=P) == _lib.NVC_ERR_SHAPE                              # both
+    assert call(loss=4) == _lib.NVC_ERR_SHAPE
+    assert call(scale=-1.0) == _lib.NVC_ERR_SHAPE
+    assert call(table=None) == _lib.NVC_ERR_NULL
+    assert call(wsp=None) == _lib.NVC_ERR_WORKSPACE
+    assert call(plan=None) == _lib.NVC_ERR_WORKSPACE
+    assert call(plan_bytes=pb - 1) == _lib.NVC_ERR_WORKSPACE
+    assert call(batch=0, table=None, plan=None, wsp=None) == 0

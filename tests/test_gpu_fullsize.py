@@ -92,9 +92,12 @@ def _grad_report(name, got, ref, bound):
     return err, rel
 
 
-@pytest.mark.parametrize("dtype,rel_tol", [("f32", 1e-4), ("f16", 3e-2), ("bf16", 1e-1)])
-def test_train_step_production_batch_against_oracle(dtype, rel_tol):
-    """2^18 samples from the 1080p G-buffer (the batch the frame trains on) through nvc_train_step."""
+@pytest.mark.parametrize("dtype,rel_tol,planned", [("f32", 1e-4, False), ("f16", 3e-2, False), ("bf16", 1e-1, False),
+                                                   ("f16", 3e-2, True)])
+def test_train_step_production_batch_against_oracle(dtype, rel_tol, planned):
+    """2^18 samples from the 1080p G-buffer (the batch the frame trains on) through nvc_train_step; planned:
+    through nvc_train_step_planned with the routing plan computed beforehand on another stream (the way
+    FramePipeline runs it), waited for by an event."""
     wl = get_workload("train_1080p")
     sc = scene(wl)
     p = params(wl)
@@ -104,8 +107,20 @@ def test_train_step_production_batch_against_oracle(dtype, rel_tol):
     rng = np.random.default_rng(41)
     pix = np.sort(rng.integers(0, n, b)).astype(np.int32)          # sorted, as nvc_select_pixels returns
     y = (rng.uniform(size=(b, wl.n_lights)) > 0.35).astype(np.uint8)
-    print(f"production-batch gradients {dtype}: {b} samples", flush=True)
-    cache.gradients(t(sc["pos_unit"]), labels=t(y), pix=t(pix), batch=b)
+    print(f"production-batch gradients {dtype}{' planned' if planned else ''}: {b} samples", flush=True)
+    if planned:
+        pos_t, pix_t = t(sc["pos_unit"]), t(pix)
+        other = torch.cuda.Stream()
+        plan = cache.new_plan(b)
+        plan.fill_(0xFF)                                       # stale contents must not matter
+        other.wait_stream(torch.cuda.current_stream())
+        cache.plan(pos_t, pix_t, b, plan, stream=other)
+        done = torch.cuda.Event()
+        done.record(other)
+        torch.cuda.current_stream().wait_event(done)
+        cache.gradients(pos_t, labels=t(y), pix=pix_t, batch=b, plan=plan)
+    else:
+        cache.gradients(t(sc["pos_unit"]), labels=t(y), pix=t(pix), batch=b)
     pos = sc["pos_unit"][pix]
     ref = bounds.gradient_error_bounds(pos, p["table"], p["weights"], wl.grid.base_res, wl.grid.growth, labels=y,
                                        dtype=dtype)

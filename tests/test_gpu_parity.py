@@ -207,6 +207,37 @@ def test_wrs_dyadic_weights_distribution():
     assert stats.chisquare(counts[p > 0], n * p[p > 0]).pvalue > 1e-3
 
 
+def test_wrs_lights_with_zero_weight():
+    """Lights a pixel cannot see weigh exactly zero: in its surface plane (n.d = 0), on the pixel itself
+    (d^2 clamped), behind the surface, or of zero intensity; mixed with ordinary lights, on a floor whose
+    waves see some lights from every pixel and others from none.  Bit for bit against the oracle."""
+    from paper_2506_05930_amd import api
+    n = 4096 + 17
+    rng = np.random.default_rng(31)
+    pos = np.zeros((n, 3), np.float32)
+    pos[:, 0] = rng.uniform(0, 8, n)
+    pos[:, 2] = rng.uniform(0, 8, n)
+    pos[: n // 2] = np.round(pos[: n // 2] * 4) / 4          # repeated positions on a grid
+    nrm = np.tile(np.array([[0, 1, 0]], np.float32), (n, 1))
+    lights = np.array([[2, 0, 3, 1.0],                        # in the floor plane: n.d = 0 everywhere
+                       [pos[5, 0], 0, pos[5, 2], 2.0],        # on a pixel
+                       [4, -2, 4, 1.5],                       # below the floor
+                       [3, 2, 3, 0.0],                        # zero intensity
+                       [1, 3, 1, 1.0], [6, 1.5, 2, 0.7], [4, 5, 7, 1.2], [7, 0.5, 7, 0.9]], np.float32)
+    vis = random_visibility(5, n, 8, np.float16)
+    out = {k: torch.empty(n, dtype=d, device=DEV) for k, d in
+           (("idx", torch.int32), ("pmf", torch.float32), ("wsum", torch.float32), ("di", torch.float32))}
+    api.nvc_sample_wrs(t(vis), t(pos), t(nrm), t(lights), 1e-3, 2, 5, out["idx"], out["pmf"], out["wsum"],
+                       out["di"])
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = pipeline.sample(vis, pos, nrm, lights, seed=2, frame=5, floor=1e-3)
+    assert np.array_equal(got["idx"], ref["idx"])
+    assert np.array_equal(got["wsum"], ref["wsum"])
+    assert np.array_equal(got["pmf"], ref["pmf"])
+    assert np.allclose(got["di"], ref["di"], rtol=2e-5, atol=1e-6 * np.abs(ref["di"]).max())
+    assert not np.isin(got["idx"], [0, 1, 2, 3]).any()      # zero-weight lights are never picked
+
+
 def test_wrs_all_lights_behind_surface():
     from paper_2506_05930_amd import api
     pos = np.zeros((3, 3), np.float32)
