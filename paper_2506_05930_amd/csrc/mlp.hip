@@ -385,8 +385,15 @@ template <class C, bool PRE> constexpr int infer_waves() {
 
 // PRE: the encoding comes from a.enc (nvc_mlp_forward) instead of the table.
 // LEAKY: leaky ReLU hidden activation, else ReLU.
+// Waves per SIMD the compiler must leave room for: three for the 16-bit 64-wide network with two
+// features per level (146 registers, no spills), whose gathers then have a third wave to hide behind
+// (1080p frame 0.983 -> 0.96 ms with the three-stream schedule); the others keep their natural
+// occupancy (the paper's network would spill at three).
+template <class C> constexpr int infer_min_waves() { return C::DT != DT_F32 && C::WB == 4 && C::F == 2 ? 3 : 1; }
+
 template <class C, bool PRE, bool LEAKY>
-__global__ __launch_bounds__((64 * infer_waves<C, PRE>())) void infer_kernel(InferArgs a) {
+__global__ __launch_bounds__((64 * infer_waves<C, PRE>())) __attribute__((amdgpu_waves_per_eu(infer_min_waves<C>())))
+void infer_kernel(InferArgs a) {
     constexpr int DT = C::DT;
     using M = Mma<DT>;
     using E = typename M::elem;
