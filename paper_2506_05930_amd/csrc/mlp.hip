@@ -600,11 +600,12 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     const int64_t pts = 16 * C::NSUB_INFER;
     const int64_t ntiles = (n + pts - 1) / pts;
     // Many more blocks than the CUs hold at once (each a short contiguous tile
-    // range): blocks that finish early are replaced, and a kernel running on
-    // another stream (the training half of a frame) gets CUs block by block.
-    // 24 per CU measured best for the 1080p frame (4 -> 24: frame 1.17 -> 1.13
-    // ms); one block per CU when the weights fill the LDS.
-    const int per_cu = smem > 80 * 1024 ? 1 : (smem > 40 * 1024 ? 2 : 24);
+    // range): blocks that finish early are replaced, and kernels running on
+    // the other streams of a frame get CUs block by block.  16 per CU for the
+    // three-stream frame (24 had measured best with two streams: 4 -> 24,
+    // frame 1.17 -> 1.13 ms; with three, 6 to 16 are about 10 us faster per
+    // frame than 24 or 4); one block per CU when the weights fill the LDS.
+    const int per_cu = smem > 80 * 1024 ? 1 : (smem > 40 * 1024 ? 2 : 16);
     const int IW = enc ? infer_waves<C, true>() : infer_waves<C, false>();
     int64_t want = (ntiles + IW - 1) / IW;                  // at least one tile per wave
     int64_t G = std::min<int64_t>(want, (int64_t)cu_count() * per_cu);
