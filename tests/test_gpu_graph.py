@@ -158,38 +158,53 @@ def test_pipelined_frames_match_joined_frames(scene):
     _params_close(joined, piped, "after four frames")
 
 
-@pytest.mark.parametrize("name", ["1080p", "paper_world"])
+@pytest.mark.parametrize("name", ["1080p", "paper_world", "clustered", "fused_labels"])
 def test_frame_pipeline_matches_joined_frames(scene, name):
-    """FramePipeline (inference + WRS, gradient pass + Adam, and the next frame's pixels and labels on three
-    streams) over four frames queued without a host synchronisation, against four joined frames: every
-    output of the first frame, the later frames within what the order of the gradient atomics allows, the
-    parameters and the loss.  The paper's configuration adds the world-space points (double-buffered with
-    the pixels)."""
+    """FramePipeline (inference + WRS, gradient pass + Adam, and the next frame's pixels, labels and routing
+    plan on three streams) over four frames queued without a host synchronisation, against four joined
+    frames: every output of the first frame, the later frames within what the order of the gradient
+    atomics allows, the parameters and the loss.  Cases: the 1080p network; the paper's configuration
+    with its world-space points (double-buffered with the pixels); the clustered cache (256 lights in 32
+    k-means clusters: one ray per cluster, the two-step pick); labels computed inside the training kernel
+    (the prep stream then only picks the pixels)."""
     from paper_2506_05930_amd.cache import FramePipeline
     from workloads import get_workload
     from workloads.scenes import SCENE_EXTENT
-    if name == "1080p":
-        wl, batch = p1080(), 4096
-    else:
+    sc = scene
+    kw = {}
+    if name == "paper_world":
         wl = get_workload("paper_1080p")
         batch = wl.train_batch
+    elif name == "clustered":
+        wl = get_workload("clustered_1080p", n_lights=256)
+        sc = box_scene(0, 160, 90, 64, 256, 256)
+        batch = 4096
+    else:
+        wl, batch = p1080(), 4096
+        if name == "fused_labels":
+            kw = {"fused_labels": True}
     p = params(wl)
-    args = [t(scene[k]) for k in ("pos_unit", "pos", "nrm", "lights", "spheres")]
-    joined, piped = make_cache(wl, p), make_cache(wl, p)
+    args = [t(sc[k]) for k in ("pos_unit", "pos", "nrm", "lights", "spheres")]
+    joined, piped = make_cache(wl, p, **kw), make_cache(wl, p, **kw)
     if wl.world_batch:
         for c in (joined, piped):
             c.set_world_samples(wl.world_batch, wl.world_box, SCENE_EXTENT)
+    if name == "clustered":
+        off, mem = api.nvc_cluster_lights(sc["lights"], 32)
+        for c in (joined, piped):
+            c.set_clusters(off, mem, n_cand=8)
+    keys = ("idx", "weight", "cluster") if name == "clustered" else ("idx", "pmf", "wsum", "di")
     side = torch.cuda.Stream()
     out_j = []
     for f in range(4):
         b = joined.frame(*args, frame=f, batch=batch, side=side)
         torch.cuda.synchronize()
-        out_j.append({"vis": b["vis"].clone(), **{k: b["sample"][k].clone() for k in ("idx", "pmf", "wsum", "di")}})
+        out_j.append({"vis": b["vis"].clone(), **{k: b["sample"][k].clone() for k in keys}})
     pipe = FramePipeline(piped, *args, batch)
     out_p = []
     for f in range(4):                                  # queued back to back
         b = pipe.run(f)
-        out_p.append({"vis": b["vis"].clone(), **{k: b["sample"][k].clone() for k in ("idx", "pmf", "wsum", "di")}})
+        out_p.append({"vis": b["vis"].clone(), **{k: b["sample"][k].clone() for k in keys}})
     pipe.finish()
     torch.cuda.synchronize()
     assert joined.step == piped.step == 4
