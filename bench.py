@@ -39,7 +39,9 @@ STAGES = ["infer", "wrs", "pixels", "labels", "train", "adam"]
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed frames (the timed region ends with one frame of look-ahead work that no later frame "
+                         "overlaps, so short runs overstate the per-frame time)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="train_1080p")
     ap.add_argument("--dtype", default=None, help="override the MLP dtype (f32, f16, bf16)")
