@@ -685,27 +685,18 @@ __global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __res
 // Shapes that get the in-kernel shadow labels: one 16-output block or two (at most 32 lights).
 template <class C> constexpr bool shadow_built() { return train_built<C>() && C::NOUTB <= 2; }
 
-// Persistent grid: as many blocks as stay resident (by the occupancy the
-// runtime reports for this kernel and LDS size; 2 per CU if it cannot say),
-// at most one per iteration.
-template <class C> static int train_blocks_per_cu(size_t smem) {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, train_kernel<C, false>, 256, smem) != hipSuccess || n < 1) {
-        (void)hipGetLastError();
-        n = 2;
-    }
-    return n;
-}
-
-// The in-kernel-label variant runs on the same grid (its blocks take the same iterations, so given the
-// same labels its gradients are the plain kernel's bit for bit; blocks beyond its residency wait).
+// Persistent grid: one block per CU (every shape fits at least one), at most one per iteration.
+// Alone, two per CU (all the resident slots) is faster, but a frame runs this kernel beside
+// inference and the next frame's labels: with one block per CU the 1080p frame took 0.921 ms against
+// 0.945-0.951 with two (1.5 per CU: 0.931; 0.75: 0.98; 0.5: 1.17), and the per-block weight partials
+// and routing offsets halve.  The in-kernel-label variant runs on the same grid (its blocks take the
+// same iterations, so given the same labels its gradients are the plain kernel's bit for bit).
 static int train_grid(const GridHost& gh, const NetShape& s, int64_t batch, size_t cursor_bytes) {
+    (void)gh;
+    (void)s;
+    (void)cursor_bytes;
     const int64_t iters = (batch + kTrainPts - 1) / kTrainPts;
-    int per_cu = 2;
-    dispatch_config(gh.n_feat, s, [&]<class C>() {
-        if constexpr (train_built<C>()) per_cu = train_blocks_per_cu<C>(TrainShape<C>::SMEM + cursor_bytes);
-    });
-    int64_t g = (int64_t)cu_count() * per_cu;
+    int64_t g = (int64_t)cu_count();
     if (g > iters) g = iters;
     if (g < 1) g = 1;
     return (int)g;

@@ -6,7 +6,7 @@ of the encode + MLP kernel walks several tiles through its next-tile
 prefetch; a seeded 65,536-pixel subset is compared with the oracle element
 by element, against the FP32 / FP16 targets and against the element-wise
 rounding bound of the forward pass (oracle/bounds.py).  The training pass
-runs on the production batch of 2^18 samples (eight persistent iterations
+runs on the production batch of 2^18 samples (sixteen persistent iterations
 per training block, weight-gradient accumulators, loss, record maxima and
 routing cursors carried across them) and is compared with the oracle's
 gradient of the whole batch, entry by entry, against the element-wise
