@@ -266,19 +266,21 @@ def run_mlp(args, wl, cache, pos_unit, dev):
 
 
 def run_loop(args, wl, cache, scene, tens, dev):
-    """The frame loop: light 0 moves on a circle; each frame is one replay of a recorded HIP graph."""
+    """The frame loop: light 0 moves on a circle; each frame is one replay of a recorded HIP graph (the
+    three-stream frame, with the next frame's light, training pixels, labels and routing plan prepared
+    beside this frame's work)."""
     import numpy as np
     import torch
 
     from paper_2506_05930_amd import api
-    from paper_2506_05930_amd.cache import FrameGraph
+    from paper_2506_05930_amd.cache import PipelineGraph
     from workloads import LightAnimation, moving_light_table
 
     pos_unit, pos, nrm, lights, spheres = tens
     n_frames = args.loop
     table = torch.as_tensor(moving_light_table(scene["lights"], wl.frames or 60)).to(dev)
-    fg = FrameGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch)
-    fg.pre = LightAnimation(table, lights, fg.ctr)
+    fg = PipelineGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch,
+                       make_anim=lambda li, ctr: LightAnimation(table, li, ctr))
     fg.capture()
     n_pix = pos_unit.shape[0]
     sub = torch.as_tensor(np.random.default_rng(3).choice(n_pix, size=min(args.loop_eval, n_pix), replace=False)
@@ -316,6 +318,7 @@ def run_loop(args, wl, cache, scene, tens, dev):
         print(json.dumps(rec), file=sys.stderr, flush=True)
     ms = [r["ms"] for r in frames]
     return {"workload": "loop_60f", "frames": n_frames, "warmup_frames": args.warmup, "graph": True,
+            "schedule": "inference + WRS, gradients + Adam, next frame's light, pixels, labels and plan on three streams",
             "ms_per_frame_mean": float(np.mean(ms)), "ms_per_frame_median": float(np.median(ms)),
             "per_frame": frames}
 

@@ -548,6 +548,224 @@ class FrameGraph:
             pass
 
 
+class PipelineGraph:
+    """FramePipeline's frames recorded as HIP graphs and replayed, one replay per frame.
+
+    Replay of frame f: on the recorded stream the light animation of frame f (`anim`, e.g.
+    LightAnimation on `lights` and `ctr`), inference and WRS + DI; on a second stream the gradient pass
+    on the pixel/label set of frame f and, once inference is done, Adam and the repack; on a third the
+    animation of frame f + 1 into a second light buffer (`lights_next`, through `anim_next`) and frame
+    f + 1's training pixels (and world-space points), shadow labels and routing plan into the other
+    set.  Both streams fork after the animation and join back before the counter increments that end
+    the graph.  The frame number and the Adam step come from device counters (`ctr`: frame f and the
+    step; `ctr_next`: frame f + 1), so every replay is the next frame; two graphs, one per set,
+    alternate.  The first replay computes the first frame's set beforehand.  Each frame computes what
+    the frames run one after another compute (its labels with its own lights).  `make_anim(lights, ctr)`
+    returns the animation of a light buffer driven by a counter block, or None for static lights.
+    Recording follows FrameGraph's rules (no allocation, every forked stream joined).
+    """
+
+    def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, make_anim=None,
+                 frame0: int = 0):
+        dev = cache.device
+        self.cache = cache
+        self.args = (pos_unit, pos_scene, nrm, lights, spheres)
+        self.batch = int(batch)
+        self.stream = torch.cuda.Stream(device=dev)
+        self.train = torch.cuda.Stream(device=dev)
+        self.prep = torch.cuda.Stream(device=dev)
+        self.ctr = api.new_counters(frame0, cache.step + 1, device=dev)
+        self.ctr_next = api.new_counters(frame0 + 1, cache.step + 2, device=dev)
+        self.frame = int(frame0)                     # host mirror of the next frame to replay
+        self.lights_next = lights.clone() if make_anim is not None else lights
+        self.anim = make_anim(lights, self.ctr) if make_anim is not None else None
+        self.anim_next = make_anim(self.lights_next, self.ctr_next) if make_anim is not None else None
+        n, m = pos_unit.shape[0], cache.mlp.n_out
+        self.bufs = {"vis": torch.empty((n, m), dtype=cache.vis_dtype, device=dev), "sample": None}
+        world = getattr(cache, "world", None)
+        self.n_world = world[0] if world is not None else 0
+        self.sets = []
+        for _ in range(2):
+            st = {"pix": torch.empty(self.batch, dtype=torch.int32, device=dev),
+                  "labels": torch.empty((self.batch, m), dtype=torch.uint8, device=dev),
+                  "plan": cache.new_plan(self.batch)}
+            if self.n_world:
+                st["wpos"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
+                st["wunit"] = torch.empty((self.n_world, 3), dtype=torch.float32, device=dev)
+                st["wlabels"] = torch.empty((self.n_world, m), dtype=torch.uint8, device=dev)
+            self.sets.append(st)
+        if cache.clustered:
+            self.bufs["sample"] = {"idx": torch.empty(n, dtype=torch.int32, device=dev),
+                                   "weight": torch.empty(n, dtype=torch.float32, device=dev),
+                                   "cluster": torch.empty(n, dtype=torch.int32, device=dev)}
+        else:
+            self.bufs["sample"] = {"idx": torch.empty(n, dtype=torch.int32, device=dev),
+                                   "pmf": torch.empty(n, dtype=torch.float32, device=dev),
+                                   "wsum": torch.empty(n, dtype=torch.float32, device=dev),
+                                   "di": torch.empty(n, dtype=torch.float32, device=dev)}
+        self.inferred = torch.cuda.Event()
+        self.pix_ws = cache.pixel_workspace(n)
+        cache._ensure_workspace(max(self.batch, self.n_world))
+        self.exec = [None, None]
+        self._prepared = False
+
+    def _prepare(self, s, stream, ctr, lights):
+        """Training pixels (+ world-space points), shadow labels and routing plan of the frame in `ctr`."""
+        c = self.cache
+        pos_unit, pos_scene = self.args[0], self.args[1]
+        spheres = self.args[4]
+        fused = c.fused_labels and not c.clustered
+        api.nvc_select_pixels(c.seed, 0, pos_unit.shape[0], s["pix"], self.pix_ws, stream, ctr=ctr)
+        if not fused:
+            if c.clustered:
+                api.nvc_shadow_labels_clustered(pos_scene, s["pix"], lights, c.cl_offsets, c.cl_members, spheres,
+                                                c.seed, 0, s["labels"], stream, ctr=ctr)
+            else:
+                api.nvc_shadow_labels(pos_scene, s["pix"], lights, spheres, s["labels"], stream)
+            c.plan(pos_unit, s["pix"], self.batch, s["plan"], stream=stream)
+        if self.n_world:
+            _, box, extent = c.world
+            api.nvc_world_samples(c.seed, 0, box, extent, s["wpos"], s["wunit"], stream, ctr=ctr)
+            if not fused:
+                if c.clustered:
+                    api.nvc_shadow_labels_clustered(s["wpos"], None, lights, c.cl_offsets, c.cl_members, spheres,
+                                                    c.seed, 0, s["wlabels"], stream, ctr=ctr)
+                else:
+                    api.nvc_shadow_labels(s["wpos"], None, lights, spheres, s["wlabels"], stream)
+
+    def _body(self, k: int):
+        """One frame that trains on set k and prepares set 1 - k, recorded (or run) on self.stream."""
+        c = self.cache
+        main = self.stream
+        pos_unit, pos_scene, nrm, lights, spheres = self.args
+        if self.anim is not None:
+            self.anim(main)
+        api.fork(self.train, main)
+        api.fork(self.prep, main)
+        c.infer(pos_unit, self.bufs["vis"], stream=main)
+        self.inferred.record(main)
+        self.bufs["sample"] = c.sample(self.bufs["vis"], pos_scene, nrm, lights, 0, self.bufs["sample"],
+                                       stream=main, ctr=self.ctr)
+        if self.anim_next is not None:
+            with torch.cuda.stream(self.prep):
+                self.anim_next(self.prep)
+        self._prepare(self.sets[1 - k], self.prep, self.ctr_next, self.lights_next)
+        s = self.sets[k]
+        fused = c.fused_labels and not c.clustered
+        if fused:
+            c.gradients_shadow(pos_unit, pos_scene, lights, spheres, pix=s["pix"], batch=self.batch,
+                               stream=self.train)
+            if self.n_world:
+                c.gradients_shadow(s["wunit"], s["wpos"], lights, spheres, batch=self.n_world, stream=self.train)
+        else:
+            c.gradients(pos_unit, labels=s["labels"], pix=s["pix"], batch=self.batch, stream=self.train,
+                        plan=s["plan"])
+            if self.n_world:
+                c.gradients(s["wunit"], labels=s["wlabels"], batch=self.n_world, stream=self.train)
+        self.train.wait_event(self.inferred)
+        c.adam(self.train, ctr=self.ctr)
+        api.join(main, self.train)
+        api.join(main, self.prep)
+        api.nvc_counters_advance(self.ctr, main)
+        api.nvc_counters_advance(self.ctr_next, main)
+
+    def _prologue(self):
+        """The first frame's set, computed eagerly before the first replay (its lights animated first)."""
+        main = self.stream
+        main.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(main):
+            if self.anim is not None:
+                self.anim(main)
+            self._prepare(self.sets[self.frame % 2], main, self.ctr, self.args[3])
+        torch.cuda.current_stream().wait_stream(main)
+        self._prepared = True
+
+    def _capture(self, k: int):
+        torch.cuda.synchronize()
+        st = self.stream
+        saved = (self.ctr.clone(), self.ctr_next.clone())
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):                # warm-up of the recorded torch work, then restore the state
+            if self.anim is not None:
+                self.anim(st)
+                self.anim_next(st)
+        torch.cuda.synchronize()
+        self.ctr.copy_(saved[0])
+        self.ctr_next.copy_(saved[1])
+        torch.cuda.synchronize()
+        ledger = api.CaptureLedger(st.cuda_stream)
+        n_alloc = FrameGraph._allocations()
+        api.nvc_graph_begin(st)
+        problem = None
+        try:
+            with torch.cuda.stream(st), api.recording(ledger):
+                self._body(k)
+                try:
+                    ledger.check()
+                except RuntimeError as e:
+                    problem = e
+                    api.join(st, self.train)
+                    api.join(st, self.prep)
+        except BaseException:
+            try:
+                api.nvc_graph_destroy(api.nvc_graph_end(st))
+            except Exception:
+                pass
+            raise
+        ex = api.nvc_graph_end(st)
+        if problem is None and FrameGraph._allocations() != n_alloc:
+            problem = RuntimeError("graph recording: device memory was allocated while recording")
+        if problem is not None:
+            api.nvc_graph_destroy(ex)
+            raise problem
+        self.exec[k] = ex
+        torch.cuda.synchronize()
+
+    def capture(self):
+        for k in (0, 1):
+            if self.exec[k] is None:
+                self._capture(k)
+        return self
+
+    def replay(self):
+        """Replay the next frame (on self.stream, ordered after the current stream's work so far)."""
+        self.capture()
+        if not self._prepared:
+            self._prologue()
+        st = self.stream
+        st.wait_stream(torch.cuda.current_stream())
+        api.nvc_graph_launch(self.exec[self.frame % 2], st)
+        torch.cuda.current_stream().wait_stream(st)
+        self.cache.step += 1
+        self.frame += 1
+
+    def run_eager(self):
+        """The same frame without the graph (the counters advance the same way)."""
+        if not self._prepared:
+            self._prologue()
+        st = self.stream
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            self._body(self.frame % 2)
+        torch.cuda.current_stream().wait_stream(st)
+        self.cache.step += 1
+        self.frame += 1
+
+    def close(self):
+        if any(e is not None for e in self.exec):
+            torch.cuda.synchronize()
+            for k in (0, 1):
+                if self.exec[k] is not None:
+                    api.nvc_graph_destroy(self.exec[k])
+                    self.exec[k] = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class NVCFunction(torch.autograd.Function):
     """vis = sigmoid(MLP(encode(pos))) with gradients for the table and the FP32 master weights.
 
