@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "kernel_config.hpp"
@@ -338,6 +339,44 @@ __device__ inline void decode_enc(int enc_dtype, int n_in, bool vec, int grp, co
     }
 }
 
+// load_enc_raw / decode_enc for an encoding in the network's 16-bit dtype
+// whose rows are whole 16-feature blocks, 8-byte aligned: one 8-byte load per
+// block and lane, no branches (the same words and values as the general
+// forms take for such an encoding).
+template <int NINB>
+__device__ inline void load_enc16(const void* enc, int n_in, int64_t p, int grp, uint32_t (&raw)[NINB][4]) {
+#pragma unroll
+    for (int b = 0; b < NINB; ++b) {
+        const uint2 v = *reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(enc) + p * n_in + 16 * b +
+                                                        4 * grp);
+        raw[b][0] = v.x; raw[b][1] = v.y; raw[b][2] = 0; raw[b][3] = 0;
+    }
+}
+
+template <int DT, int NINB>
+__device__ inline void decode_enc16(const uint32_t (&raw)[NINB][4], float (&act)[NINB][4]) {
+#pragma unroll
+    for (int b = 0; b < NINB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t h = (raw[b][i / 2] >> (16 * (i % 2))) & 0xffffu;
+            act[b][i] = DT == DT_F16 ? (float)__builtin_bit_cast(_Float16, (uint16_t)h) : __uint_as_float(h << 16);
+        }
+}
+
+// A vector store marked non-temporal (streamed past the caches' normal
+// allocation).  The visibilities are the largest write of a frame (133 MB at
+// 1080p x 32 lights, 2.1 GB at 4K x 128) and are read once, by the light
+// pick; written through the caches they evict the hash table that the next
+// tiles gather from.  Measured: 4K x 128 inference alone 1.84 -> 1.41 ms,
+// the 1080p frame 0.920 -> 0.904 ms, the paper's configuration 0.342 ->
+// 0.334 ms.
+template <class V>
+__device__ inline void stream_store(V v, void* p) {
+    typedef uint32_t wN __attribute__((ext_vector_type(sizeof(V) / 4)));
+    __builtin_nontemporal_store(__builtin_bit_cast(wN, v), reinterpret_cast<wN*>(p));
+}
+
 // Visibilities v[0..N-1] of lights l0..l0+N-1 (N = 4 or 8) at point p, in
 // the output dtype.
 template <int N>
@@ -347,19 +386,19 @@ __device__ inline void store_vis(const InferArgs& a, int64_t p, int l0, const fl
     if (vec && a.vis_dtype == DT_F32) {
 #pragma unroll
         for (int q = 0; q < N; q += 4)
-            *reinterpret_cast<float4*>((float*)a.vis + base + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+            stream_store(make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]), (float*)a.vis + base + q);
     } else if (vec && a.vis_dtype == DT_F16) {
         typedef _Float16 hN __attribute__((ext_vector_type(N)));
         hN o;
 #pragma unroll
         for (int i = 0; i < N; ++i) o[i] = (_Float16)v[i];
-        *reinterpret_cast<hN*>((_Float16*)a.vis + base) = o;
+        stream_store(o, (_Float16*)a.vis + base);
     } else if (vec) {
         typedef __bf16 bN __attribute__((ext_vector_type(N)));
         bN o;
 #pragma unroll
         for (int i = 0; i < N; ++i) o[i] = (__bf16)v[i];
-        *reinterpret_cast<bN*>((__bf16*)a.vis + base) = o;
+        stream_store(o, (__bf16*)a.vis + base);
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -391,9 +430,19 @@ template <class C, bool PRE> constexpr int infer_waves() {
 // occupancy (the paper's network would spill at three).
 template <class C> constexpr int infer_min_waves() { return C::DT != DT_F32 && C::WB == 4 && C::F == 2 ? 3 : 1; }
 
-template <class C, bool PRE, bool LEAKY>
+// V16 (with PRE): the encoding and the visibilities in the network's 16-bit dtype, rows of whole
+// 16-wide blocks (infer_v16_ok): branch-free loads and stores, so that the stores of a tile stay in
+// flight under the next tile's matrix work.  The memory counter of a wave counts loads and stores
+// together, in order; with a data-dependent branch around a store (the check against the last point)
+// or a store whose width depends on the output dtype, the compiler cannot tell how many stores follow
+// the next tile's loads, and waits for all of them before that tile.  The stores go through a buffer
+// resource that covers the tile's rows of the output (clipped at its end): the hardware's range check
+// drops the lanes past the last point.  These stores keep the default cache policy (4K x 128 network:
+// 0.96 ms against 0.99 with the non-temporal one; nothing here gathers from a table).
+template <class C, bool PRE, bool LEAKY, bool V16 = false>
 __global__ __launch_bounds__((64 * infer_waves<C, PRE>())) __attribute__((amdgpu_waves_per_eu(infer_min_waves<C>())))
 void infer_kernel(InferArgs a) {
+    static_assert(!V16 || (PRE && C::DT != DT_F32), "V16 is the 16-bit form of the encoding-input kernel");
     constexpr int DT = C::DT;
     using M = Mma<DT>;
     using E = typename M::elem;
@@ -429,7 +478,8 @@ void infer_kernel(InferArgs a) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // V16: the wave index made wave-uniform, so that the tile bounds and the store resource are scalars.
+    const int wave = V16 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
     const int grp = lane >> 4;
     const int col = lane & 15;
     constexpr int PTS = 16 * NSUB;
@@ -459,7 +509,9 @@ void infer_kernel(InferArgs a) {
         for (int s = 0; s < NSUB; ++s) {
             const int64_t p = tt * PTS + s * 16 + col;
             const int64_t pc = p < a.n ? p : a.n - 1;
-            if constexpr (PRE) {
+            if constexpr (V16) {
+                load_enc16<C::NINB>(a.enc, a.n_in, pc, grp, raw[s]);
+            } else if constexpr (PRE) {
                 load_enc_raw<C::NINB>(a.enc, a.enc_dtype, a.n_in, a.enc_vec != 0, pc, grp, raw[s]);
             } else {
 #pragma unroll
@@ -471,15 +523,22 @@ void infer_kernel(InferArgs a) {
     auto stage = [&](int64_t t, float (&h0)[NSUB][C::NINB][4]) {
 #pragma unroll
         for (int s = 0; s < NSUB; ++s) {
-            if constexpr (PRE)
+            if constexpr (V16)
+                decode_enc16<DT, C::NINB>(raw[s], h0[s]);
+            else if constexpr (PRE)
                 decode_enc<C::NINB>(a.enc_dtype, a.n_in, a.enc_vec != 0, grp, raw[s], h0[s]);
             else
                 encode_lane_lv<C::F, C::NINB>(a.table, lv, clamp_unit(px[s][0]), clamp_unit(px[s][1]),
                                               clamp_unit(px[s][2]), h0[s]);
         }
-        if (t + IW < t1) fetch(t + IW);
+        // (V16: also past the wave's last tile, at the clamped last point, so that every iteration
+        // issues the same loads.)
+        if (V16 || t + IW < t1) fetch(t + IW);
     };
     if (t0 + wave < t1) fetch(t0 + wave);
+    // V16: the first tile's loads complete before the loop, so that the loop entry and the back edge
+    // present the compiler's wait insertion with the same outstanding operations (vmcnt(0) alone).
+    if constexpr (V16) __builtin_amdgcn_s_waitcnt(0x0F70);
     for (int64_t t = t0 + wave; t < t1; t += IW) {
         // Weight fragments are read from LDS (or L1) in every iteration: the
         // opaque zero offset stops the compiler from hoisting all of them into
@@ -510,9 +569,29 @@ void infer_kernel(InferArgs a) {
                 else
                     hidden_layer16<LEAKY, DT, NSUB, KCW, KCW>(w_it[k], lane, xb, xa, a.slope);
             }
+            const int64_t row = (int64_t)a.n_out * 2;          // V16: bytes per point of the output
+            const int64_t tb = t * PTS * row;
+            // 0x00020000: the descriptor's fourth word with a 32-bit data format (untyped access)
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((char*)a.vis + tb, 0, (int)min((int64_t)PTS * row, a.n * row - tb),
+                                                  0x00020000);
             auto emit = [&](int s, int c, const float (&v)[4 * GB]) {
-                const int64_t p = t * PTS + s * 16 + col;
-                if (p < a.n) store_vis<4 * GB>(a, p, 16 * GB * c + 4 * GB * grp, v);
+                if constexpr (V16) {
+                    using E16 = std::conditional_t<DT == DT_F16, _Float16, __bf16>;
+                    typedef E16 hN __attribute__((ext_vector_type(4 * GB)));
+                    hN o;
+#pragma unroll
+                    for (int i = 0; i < 4 * GB; ++i) o[i] = (E16)v[i];
+                    const int off = ((s * 16 + col) * a.n_out + 16 * GB * c + 4 * GB * grp) * 2;
+                    typedef uint32_t wN __attribute__((ext_vector_type(2 * GB)));
+                    if constexpr (GB == 2)
+                        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wN, o), rs, off, 0, 0);
+                    else
+                        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wN, o), rs, off, 0, 0);
+                } else {
+                    const int64_t p = t * PTS + s * 16 + col;
+                    if (p < a.n) store_vis<4 * GB>(a, p, 16 * GB * c + 4 * GB * grp, v);
+                }
             };
             if constexpr (C::NHID % 2 == 1)
                 output_layer16<DT, NSUB, KCW, C::NOUTB, GB>(w_it[NL - 1], lane, xa, emit);
@@ -611,6 +690,20 @@ static hipError_t run_infer(const GridDev& g, const PackPlan& plan, const float*
     int64_t G = std::min<int64_t>(want, (int64_t)cu_count() * per_cu);
     G = std::max<int64_t>(8, (G + 7) / 8 * 8);
     const bool leaky = slope != 0.0f;
+    if constexpr (C::DT != DT_F32) {
+        constexpr int GB = C::NOUTB % 2 == 0 ? 2 : 1;
+        const bool v16 = enc && vis_dtype == C::DT && enc_dtype == C::DT && n_out == 16 * C::NOUTB &&
+                         n_in == 16 * C::NINB && (uintptr_t)vis % (8 * GB) == 0 && (uintptr_t)enc % 8 == 0 &&
+                         (int64_t)pts * n_out * 2 <= INT32_MAX;
+        if (v16 && leaky) {
+            hipLaunchKernelGGL((infer_kernel<C, true, true, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+            return hipGetLastError();
+        }
+        if (v16) {
+            hipLaunchKernelGGL((infer_kernel<C, true, false, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
+            return hipGetLastError();
+        }
+    }
     if (enc && leaky)
         hipLaunchKernelGGL((infer_kernel<C, true, true>), dim3((unsigned)G), dim3(64 * IW), smem, st, a);
     else if (enc)

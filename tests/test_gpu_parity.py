@@ -152,6 +152,33 @@ def test_mlp_forward_on_encoding_equals_fused_inference(wl_name, dtype):
         assert torch.equal(out, ref), (wl_name, dtype, enc_dt)
 
 
+@pytest.mark.parametrize("wl_name,dtype,n", [("frame_1080p", "f16", 2085), ("frame_1080p", "bf16", 1000003),
+                                             ("sweep_4k", "f16", 2085), ("sweep_4k", "f16", 200003),
+                                             ("sweep_4k", "bf16", 200003), ("paper_1080p", "f16", 100003),
+                                             ("tiny", "f16", 2085)])
+def test_mlp_forward_16bit_output_equals_fused_inference(wl_name, dtype, n):
+    """nvc_mlp_forward with the visibilities in the network's 16-bit dtype, from the encoding stored in that
+    dtype (the branch-free kernel whose stores go through a per-tile buffer resource, the lanes past the last
+    point dropped by its range check) and in FP32 (the general kernel), equals nvc_infer's 16-bit output bit
+    for bit; n leaves a ragged last tile, and the larger n give every wave several tiles.  The rows of the
+    output next to the buffer (a guard row on each side) stay untouched."""
+    from paper_2506_05930_amd import api
+    wl = get_workload(wl_name)
+    cache = make_cache(wl, params(wl), dtype=dtype)
+    tdt = api.torch_dtype(cache.mlp.dtype)
+    pos = t(rand_pos(18, n))
+    ref = cache.infer(pos, dtype=tdt)
+    m = ref.shape[1]
+    for enc_dt in (tdt, torch.float32):
+        enc = cache.encode(pos, dtype=enc_dt)
+        guard = torch.full((n + 2, m), 7.0, dtype=tdt, device=DEV)
+        out = guard[1:n + 1]
+        api.nvc_mlp_forward(cache.mlp, cache.packed, enc, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (wl_name, dtype, n, enc_dt)
+        assert torch.all(guard[0] == 7.0) and torch.all(guard[n + 1] == 7.0), (wl_name, dtype, n, enc_dt)
+
+
 # ----------------------------------------------------------------- WRS
 @pytest.mark.parametrize("m,with_n,floor", [(8, False, 1e-3), (32, True, 1e-3), (32, True, 0.0), (128, True, 1e-3),
                                             (20, True, 1e-3)])
