@@ -34,6 +34,8 @@ __device__ inline float scheduled_lr(float lr, float lr_end, int decay, int t) {
     return (1.0f - frac) * lr + frac * lr_end;
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g, float* __restrict__ m,
                                                    float* __restrict__ v, int64_t count, int step,
                                                    const int32_t* __restrict__ step_dev, float lr, float lr_end,
@@ -46,17 +48,24 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float*
     const int64_t n4 = aligned ? count / 4 : 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        // The gradient and the moments are read and (the moments) written with the non-temporal
+        // policy: they are touched once per step, and through the caches they would evict the
+        // parameters (the hash table), which the next inference gathers from.  1080p frame 0.906 ->
+        // 0.896 ms, the paper's configuration 0.335 -> 0.331 ms.
         float4 P = reinterpret_cast<float4*>(p)[i];
-        float4 Gr = reinterpret_cast<float4*>(g)[i];
-        float4 Mm = reinterpret_cast<float4*>(m)[i];
-        float4 V = reinterpret_cast<float4*>(v)[i];
+        const f4v g4 = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(g) + i);
+        const f4v m4 = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(m) + i);
+        const f4v v4 = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(v) + i);
+        float4 Gr = make_float4(g4.x, g4.y, g4.z, g4.w);
+        float4 Mm = make_float4(m4.x, m4.y, m4.z, m4.w);
+        float4 V = make_float4(v4.x, v4.y, v4.z, v4.w);
         adam_one(P.x, Gr.x, Mm.x, V.x, step_size, bc2_sqrt, b1, b2, eps);
         adam_one(P.y, Gr.y, Mm.y, V.y, step_size, bc2_sqrt, b1, b2, eps);
         adam_one(P.z, Gr.z, Mm.z, V.z, step_size, bc2_sqrt, b1, b2, eps);
         adam_one(P.w, Gr.w, Mm.w, V.w, step_size, bc2_sqrt, b1, b2, eps);
         reinterpret_cast<float4*>(p)[i] = P;
-        reinterpret_cast<float4*>(m)[i] = Mm;
-        reinterpret_cast<float4*>(v)[i] = V;
+        __builtin_nontemporal_store(f4v{Mm.x, Mm.y, Mm.z, Mm.w}, reinterpret_cast<f4v*>(m) + i);
+        __builtin_nontemporal_store(f4v{V.x, V.y, V.z, V.w}, reinterpret_cast<f4v*>(v) + i);
         if (zero_grad) reinterpret_cast<float4*>(g)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
