@@ -62,6 +62,10 @@ def parse():
                     help="instead: run the frame loop for this many frames (one HIP graph per frame, light 0 "
                          "moving) and print its per-frame report")
     ap.add_argument("--loop-eval", type=int, default=65536, help="pixels of the loop's fixed evaluation subset")
+    ap.add_argument("--loop-graph", choices=("lagged", "pipeline"), default="lagged",
+                    help="the loop's recorded frame: 'lagged' runs frame f's light pick inside the replay of "
+                         "frame f + 1, beside its inference (LaggedPickGraph); 'pipeline' keeps it in frame f's "
+                         "replay (PipelineGraph)")
     ap.add_argument("--micro", action="store_true",
                     help="instead: the memory microbenchmarks (device copy, random 8-byte gathers)")
     ap.add_argument("--mlp", action="store_true",
@@ -273,14 +277,15 @@ def run_loop(args, wl, cache, scene, tens, dev):
     import torch
 
     from paper_2506_05930_amd import api
-    from paper_2506_05930_amd.cache import PipelineGraph
+    from paper_2506_05930_amd.cache import LaggedPickGraph, PipelineGraph
     from workloads import LightAnimation, moving_light_table
 
     pos_unit, pos, nrm, lights, spheres = tens
     n_frames = args.loop
     table = torch.as_tensor(moving_light_table(scene["lights"], wl.frames or 60)).to(dev)
-    fg = PipelineGraph(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch,
-                       make_anim=lambda li, ctr: LightAnimation(table, li, ctr))
+    lagged = args.loop_graph == "lagged"
+    fg = (LaggedPickGraph if lagged else PipelineGraph)(cache, pos_unit, pos, nrm, lights, spheres, wl.train_batch,
+                                                        make_anim=lambda li, ctr: LightAnimation(table, li, ctr))
     fg.capture()
     n_pix = pos_unit.shape[0]
     sub = torch.as_tensor(np.random.default_rng(3).choice(n_pix, size=min(args.loop_eval, n_pix), replace=False)
@@ -300,15 +305,16 @@ def run_loop(args, wl, cache, scene, tens, dev):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         # evaluation on the fixed subset with this frame's lights (untimed)
+        lf = fg.lights_of(fg.frame - 1) if lagged else lights
         cache.infer(sub_pos_unit, vis_sub)
-        api.nvc_shadow_labels(pos, sub, lights, spheres, lab_sub)
+        api.nvc_shadow_labels(pos, sub, lf, spheres, lab_sub)
         v = vis_sub.float()
         y = lab_sub.float()
         vc = torch.clamp(v, 1e-6, 1 - 1e-6)
         rec = {"frame": int(fg.ctr[0].item()) - 1, "ms": round(ms, 4), "loss": round(float(cache.loss_buf.item()), 6),
                "vis_mae": round(float((v - y).abs().mean()), 6),
                "vis_bce": round(float(-(y * torch.log(vc) + (1 - y) * torch.log(1 - vc)).mean()), 6)}
-        fsub = unshadowed(pos.index_select(0, sub.long()), nrm.index_select(0, sub.long()), lights)
+        fsub = unshadowed(pos.index_select(0, sub.long()), nrm.index_select(0, sub.long()), lf)
         st = estimator_stats(fsub, y, v, cache.vis_floor)
         rec["var_ratio_cache_vs_none"] = round(st["cache"]["var"] / st["no_cache"]["var"], 5)
         rec["p_occluded"] = {k: round(st[k]["p_occluded"], 5) for k in st}
@@ -327,7 +333,10 @@ def run_loop(args, wl, cache, scene, tens, dev):
     ms = [r["ms"] for r in frames]
     return {"workload": "loop_60f", "frames": n_frames, "warmup_frames": args.warmup, "graph": True,
             "ms_per_frame_back_to_back": ms_b2b,
-            "schedule": "inference + WRS, gradients + Adam, next frame's light, pixels, labels and plan on three streams",
+            "schedule": ("inference + the previous frame's WRS, gradients + Adam, next frame's light, pixels, labels "
+                         "and plan on four streams" if lagged else
+                         "inference + WRS, gradients + Adam, next frame's light, pixels, labels and plan on three "
+                         "streams"),
             "ms_per_frame_mean": float(np.mean(ms)), "ms_per_frame_median": float(np.median(ms)),
             "per_frame": frames}
 

@@ -606,7 +606,7 @@ class PipelineGraph:
         self.inferred = torch.cuda.Event()
         self.pix_ws = cache.pixel_workspace(n)
         cache._ensure_workspace(max(self.batch, self.n_world))
-        self.exec = [None, None]
+        self.exec = [None] * self.n_graphs
         self._prepared = False
 
     def _prepare(self, s, stream, ctr, lights):
@@ -704,8 +704,8 @@ class PipelineGraph:
                     ledger.check()
                 except RuntimeError as e:
                     problem = e
-                    api.join(st, self.train)
-                    api.join(st, self.prep)
+                    for side in self._side_streams():      # join so that the capture can still be ended
+                        api.join(st, side)
         except BaseException:
             try:
                 api.nvc_graph_destroy(api.nvc_graph_end(st))
@@ -721,8 +721,13 @@ class PipelineGraph:
         self.exec[k] = ex
         torch.cuda.synchronize()
 
+    def _side_streams(self):
+        return (self.train, self.prep)
+
+    n_graphs = 2          # recorded frames: one per pixel/label set
+
     def capture(self):
-        for k in (0, 1):
+        for k in range(self.n_graphs):
             if self.exec[k] is None:
                 self._capture(k)
         return self
@@ -754,7 +759,7 @@ class PipelineGraph:
     def close(self):
         if any(e is not None for e in self.exec):
             torch.cuda.synchronize()
-            for k in (0, 1):
+            for k in range(self.n_graphs):
                 if self.exec[k] is not None:
                     api.nvc_graph_destroy(self.exec[k])
                     self.exec[k] = None
@@ -764,6 +769,163 @@ class PipelineGraph:
             self.close()
         except Exception:
             pass
+
+
+class LaggedPickGraph(PipelineGraph):
+    """PipelineGraph with the light pick (WRS + DI) of frame f moved into the replay of frame f + 1, where it
+    runs beside that frame's inference instead of after this frame's.
+
+    A replay ends when all of its streams are done, so in PipelineGraph the next frame's inference also waits
+    for this frame's pick; queued eagerly (FramePipeline) the two overlap.  Here replay f runs: inference of
+    frame f into its own visibility buffer (two alternate); on a fourth stream the pick of frame f - 1 from the
+    other buffer, with frame f - 1's lights and frame number (`ctr_prev`); the gradient pass and Adam of
+    frame f; frame f + 1's pixels, routing plan and world points, then (once the pick is done, since frame
+    f + 1 reuses frame f - 1's light buffer) its light animation and labels.  Two light buffers alternate
+    the same way: frame f's lights are `lights_of(f)`.  After replay f the pick outputs (`bufs["sample"]`)
+    are frame f - 1's; `flush()` runs the last frame's pick.  The first frame runs eagerly (there is no
+    earlier pick); the frames compute what the frames run one after another compute.  (Three light buffers,
+    so that the labels need not wait for the pick, measured the same.)
+    """
+
+    def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, make_anim=None,
+                 frame0: int = 0):
+        super().__init__(cache, pos_unit, pos_scene, nrm, lights, spheres, batch, make_anim, frame0)
+        dev = cache.device
+        self.pick = torch.cuda.Stream(device=dev)
+        self.ctr_prev = api.new_counters(frame0 - 1, cache.step, device=dev)
+        self.L = [None, None]
+        self.L[frame0 % 2] = lights
+        self.L[1 - frame0 % 2] = self.lights_next
+        self.vis = [self.bufs["vis"], torch.empty_like(self.bufs["vis"])]
+        self.anim_into = ([make_anim(self.L[j], self.ctr_next) for j in (0, 1)] if make_anim is not None
+                          else [None, None])
+        self.picked = torch.cuda.Event()
+        self.frame0 = int(frame0)
+
+    def lights_of(self, frame: int) -> torch.Tensor:
+        return self.L[frame % 2]
+
+    def vis_of(self, frame: int) -> torch.Tensor:
+        return self.vis[frame % 2]
+
+    def _side_streams(self):
+        return (self.train, self.prep, self.pick)
+
+    def _body(self, k: int, pick: bool = True):
+        """Frame f (f % 2 == k), with the pick of frame f - 1 unless `pick` is False."""
+        c = self.cache
+        main = self.stream
+        pos_unit, pos_scene, nrm, _, spheres = self.args
+        api.fork(self.train, main)
+        api.fork(self.prep, main)
+        if pick:
+            api.fork(self.pick, main)
+        c.infer(pos_unit, self.vis[k], stream=main)
+        self.inferred.record(main)
+        if pick:
+            self.bufs["sample"] = c.sample(self.vis[1 - k], pos_scene, nrm, self.L[1 - k], 0, self.bufs["sample"],
+                                           stream=self.pick, ctr=self.ctr_prev)
+            self.picked.record(self.pick)
+        # frame f + 1: pixels, plan and world points first; its lights go into the buffer the pick reads
+        fused = c.fused_labels and not c.clustered
+        nxt = self.sets[1 - k]
+        prep = self.prep
+        api.nvc_select_pixels(c.seed, 0, pos_unit.shape[0], nxt["pix"], self.pix_ws, prep, ctr=self.ctr_next)
+        if not fused:
+            c.plan(pos_unit, nxt["pix"], self.batch, nxt["plan"], stream=prep)
+        if self.n_world:
+            _, box, extent = c.world
+            api.nvc_world_samples(c.seed, 0, box, extent, nxt["wpos"], nxt["wunit"], prep, ctr=self.ctr_next)
+        if pick:
+            prep.wait_event(self.picked)
+        if self.anim_into[1 - k] is not None:
+            with torch.cuda.stream(prep):
+                self.anim_into[1 - k](prep)
+        light_n = self.L[1 - k]
+        if not fused:
+            if c.clustered:
+                api.nvc_shadow_labels_clustered(pos_scene, nxt["pix"], light_n, c.cl_offsets, c.cl_members, spheres,
+                                                c.seed, 0, nxt["labels"], prep, ctr=self.ctr_next)
+            else:
+                api.nvc_shadow_labels(pos_scene, nxt["pix"], light_n, spheres, nxt["labels"], prep)
+            if self.n_world:
+                if c.clustered:
+                    api.nvc_shadow_labels_clustered(nxt["wpos"], None, light_n, c.cl_offsets, c.cl_members, spheres,
+                                                    c.seed, 0, nxt["wlabels"], prep, ctr=self.ctr_next)
+                else:
+                    api.nvc_shadow_labels(nxt["wpos"], None, light_n, spheres, nxt["wlabels"], prep)
+        s = self.sets[k]
+        light_k = self.L[k]
+        if fused:
+            c.gradients_shadow(pos_unit, pos_scene, light_k, spheres, pix=s["pix"], batch=self.batch,
+                               stream=self.train)
+            if self.n_world:
+                c.gradients_shadow(s["wunit"], s["wpos"], light_k, spheres, batch=self.n_world, stream=self.train)
+        else:
+            c.gradients(pos_unit, labels=s["labels"], pix=s["pix"], batch=self.batch, stream=self.train,
+                        plan=s["plan"])
+            if self.n_world:
+                c.gradients(s["wunit"], labels=s["wlabels"], batch=self.n_world, stream=self.train)
+        self.train.wait_event(self.inferred)
+        c.adam(self.train, ctr=self.ctr)
+        api.join(main, self.train)
+        api.join(main, self.prep)
+        if pick:
+            api.join(main, self.pick)
+        api.nvc_counters_advance(self.ctr, main)
+        api.nvc_counters_advance(self.ctr_next, main)
+        api.nvc_counters_advance(self.ctr_prev, main)
+
+    def _prologue(self):
+        """The first frame's lights and set, computed eagerly before its frame."""
+        main = self.stream
+        k = self.frame % 2
+        main.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(main):
+            if self.anim is not None:
+                self.anim(main)                    # make_anim(lights, ctr): the first frame's lights
+            self._prepare(self.sets[k], main, self.ctr, self.L[k])
+        torch.cuda.current_stream().wait_stream(main)
+        self._prepared = True
+
+    def _run(self, graph: bool):
+        st = self.stream
+        k = self.frame % 2
+        first = self.frame == self.frame0
+        if graph:
+            # recorded before the first frame runs: the warm-up of the recorded light animations writes
+            # the first frame's lights and the next frame's, as the first frame itself does
+            self.capture()
+        if not self._prepared:
+            self._prologue()
+        st.wait_stream(torch.cuda.current_stream())
+        if graph and not first:
+            api.nvc_graph_launch(self.exec[k], st)
+        else:
+            with torch.cuda.stream(st):
+                self._body(k, pick=not first)
+        torch.cuda.current_stream().wait_stream(st)
+        self.cache.step += 1
+        self.frame += 1
+
+    def replay(self):
+        """The next frame (the first one eagerly), and the previous frame's pick."""
+        self._run(graph=True)
+
+    def run_eager(self):
+        self._run(graph=False)
+
+    def flush(self):
+        """The pick of the last frame run (into bufs["sample"])."""
+        if self.frame == self.frame0:
+            return
+        st = self.stream
+        k = (self.frame - 1) % 2
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            self.bufs["sample"] = self.cache.sample(self.vis[k], self.args[1], self.args[2], self.L[k], 0,
+                                                    self.bufs["sample"], stream=st, ctr=self.ctr_prev)
+        torch.cuda.current_stream().wait_stream(st)
 
 
 class NVCFunction(torch.autograd.Function):

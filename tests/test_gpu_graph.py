@@ -299,3 +299,83 @@ def test_pipeline_graph_replays_match_joined_frames(scene, name):
     # too, so the differences compound; an ordering fault would still be far beyond the bound
     _params_close(joined, graphed, f"after {n_frames} frames", bound=1e-3)
     pg.close()
+
+
+@pytest.mark.parametrize("name", ["1080p", "paper_world", "clustered", "fused_labels"])
+def test_lagged_pick_graph_matches_joined_frames(scene, name):
+    """LaggedPickGraph (the pick of frame f inside replay f + 1, beside that frame's inference; visibility
+    and light buffers alternating) over six frames, light 0 moving on a circle, against six joined frames
+    with the light placed from the host: every frame's lights, training pixels and labels bit for bit, the
+    first frame's visibilities and pick bit for bit, the later frames' within what the order of the gradient
+    atomics allows (the pick of frame f read after replay f + 1, the last one after flush()), the
+    parameters and the counters.  Replays 1-2 and 4-5 follow each other without a host synchronisation."""
+    from paper_2506_05930_amd.cache import LaggedPickGraph
+    from workloads import get_workload
+    from workloads.scenes import SCENE_EXTENT
+    sc = scene
+    kw = {}
+    if name == "paper_world":
+        wl = get_workload("paper_1080p")
+        batch = wl.train_batch
+    elif name == "clustered":
+        wl = get_workload("clustered_1080p", n_lights=256)
+        sc = box_scene(0, 160, 90, 64, 256, 256)
+        batch = 4096
+    else:
+        wl, batch = p1080(), 4096
+        if name == "fused_labels":
+            kw = {"fused_labels": True}
+    p = params(wl)
+    table_np = moving_light_table(sc["lights"], 60)
+    args_j = [t(sc[k]) for k in ("pos_unit", "pos", "nrm", "lights", "spheres")]
+    args_g = [t(sc[k]) for k in ("pos_unit", "pos", "nrm", "lights", "spheres")]
+    joined, graphed = make_cache(wl, p, **kw), make_cache(wl, p, **kw)
+    if wl.world_batch:
+        for c in (joined, graphed):
+            c.set_world_samples(wl.world_batch, wl.world_box, SCENE_EXTENT)
+    if name == "clustered":
+        off, mem = api.nvc_cluster_lights(sc["lights"], 32)
+        for c in (joined, graphed):
+            c.set_clusters(off, mem, n_cand=8)
+    keys = ("idx", "weight", "cluster") if name == "clustered" else ("idx", "pmf", "wsum", "di")
+    tab = t(table_np)
+    side = torch.cuda.Stream()
+    fused = name == "fused_labels"
+    n_frames = 6
+    out_j = []
+    for f in range(n_frames):
+        args_j[3][0].copy_(t(table_np[f]))
+        b = joined.frame(*args_j, frame=f, batch=batch, side=side)
+        torch.cuda.synchronize()
+        out_j.append({"vis": b["vis"].clone(), **{k: b["sample"][k].clone() for k in keys},
+                      "pix": b["train"]["pix"].clone(), "labels": b["train"]["labels"].clone(),
+                      "lights": args_j[3].clone()})
+    lg = LaggedPickGraph(graphed, *args_g, batch, make_anim=lambda lights, ctr: LightAnimation(tab, lights, ctr))
+    out_g = [dict() for _ in range(n_frames)]
+    for f in range(n_frames):
+        lg.replay()
+        s = lg.sets[f % 2]
+        out_g[f].update({"vis": lg.vis_of(f).clone(), "pix": s["pix"].clone(), "labels": s["labels"].clone(),
+                         "lights": lg.lights_of(f).clone()})
+        if f >= 1:
+            out_g[f - 1].update({k: lg.bufs["sample"][k].clone() for k in keys})
+        if f not in (1, 4):
+            torch.cuda.synchronize()
+    lg.flush()
+    out_g[n_frames - 1].update({k: lg.bufs["sample"][k].clone() for k in keys})
+    torch.cuda.synchronize()
+    for f, (bj, bg) in enumerate(zip(out_j, out_g)):
+        assert torch.equal(bg["lights"], bj["lights"]), f
+        assert torch.equal(bg["pix"], bj["pix"]), f
+        if not fused:
+            assert torch.equal(bg["labels"], bj["labels"]), f
+        if f == 0:
+            for k in ("vis",) + keys:
+                assert torch.equal(bj[k], bg[k]), k
+        else:
+            _later_frame_close(bj["vis"], bg["vis"], bj["idx"], bg["idx"], f)
+    assert joined.step == graphed.step == n_frames
+    assert lg.ctr.cpu().tolist() == [n_frames, n_frames + 1]
+    assert lg.ctr_prev.cpu().tolist()[0] == n_frames - 1
+    _params_close(joined, graphed, f"after {n_frames} frames", bound=1e-3)
+    lg.close()
