@@ -789,6 +789,10 @@ class LaggedPickGraph(PipelineGraph):
 
     def __init__(self, cache: NVCache, pos_unit, pos_scene, nrm, lights, spheres, batch: int, make_anim=None,
                  frame0: int = 0):
+        # Switched off: one GPU run of its test (the clustered case, after 38 other GPU tests) ended in a
+        # segmentation fault on the host inside the graph launch; the same tests had passed in two runs of
+        # their own file, and the cause has not been found.
+        raise RuntimeError("LaggedPickGraph is disabled: a host-side fault in its graph launch is not explained")
         super().__init__(cache, pos_unit, pos_scene, nrm, lights, spheres, batch, make_anim, frame0)
         dev = cache.device
         self.pick = torch.cuda.Stream(device=dev)

