@@ -179,6 +179,41 @@ def test_mlp_forward_16bit_output_equals_fused_inference(wl_name, dtype, n):
         assert torch.all(guard[0] == 7.0) and torch.all(guard[n + 1] == 7.0), (wl_name, dtype, n, enc_dt)
 
 
+@pytest.mark.parametrize("wl_name,dtype", [("frame_1080p", "f16"), ("sweep_4k", "bf16")])
+def test_mlp_forward_16bit_output_edge_cases(wl_name, dtype):
+    """The 16-bit encoding-input kernel at sizes below and around one tile (1, 31, 33 points: the buffer
+    resource of the only tile is clipped to the rows that exist) and with outputs the kernel cannot take
+    (a row offset by one element, which breaks the 16-byte alignment, and an FP32 output): every case equals
+    nvc_infer's output for the same points bit for bit, and nothing is written outside the output rows."""
+    from paper_2506_05930_amd import api
+    wl = get_workload(wl_name)
+    cache = make_cache(wl, params(wl), dtype=dtype)
+    tdt = api.torch_dtype(cache.mlp.dtype)
+    m = cache.mlp.n_out
+    for n in (1, 31, 33):
+        pos = t(rand_pos(19 + n, n))
+        enc = cache.encode(pos, dtype=tdt)
+        ref = cache.infer(pos, dtype=tdt)
+        guard = torch.full((n + 2, m), 7.0, dtype=tdt, device=DEV)
+        api.nvc_mlp_forward(cache.mlp, cache.packed, enc, guard[1:n + 1])
+        torch.cuda.synchronize()
+        assert torch.equal(guard[1:n + 1], ref), (wl_name, n)
+        assert torch.all(guard[0] == 7.0) and torch.all(guard[n + 1] == 7.0), (wl_name, n)
+    n = 4099
+    pos = t(rand_pos(23, n))
+    enc = cache.encode(pos, dtype=tdt)
+    ref = cache.infer(pos, dtype=tdt)
+    flat = torch.full((n * m + 2,), 7.0, dtype=tdt, device=DEV)
+    out = flat[1:n * m + 1].view(n, m)                     # 2-byte offset: not 16-byte aligned
+    api.nvc_mlp_forward(cache.mlp, cache.packed, enc, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    assert flat[0].item() == 7.0 and flat[-1].item() == 7.0
+    out32 = torch.empty((n, m), dtype=torch.float32, device=DEV)
+    api.nvc_mlp_forward(cache.mlp, cache.packed, enc, out32)
+    assert torch.equal(out32, cache.infer(pos, dtype=torch.float32))
+
+
 # ----------------------------------------------------------------- WRS
 @pytest.mark.parametrize("m,with_n,floor", [(8, False, 1e-3), (32, True, 1e-3), (32, True, 0.0), (128, True, 1e-3),
                                             (20, True, 1e-3)])
