@@ -259,24 +259,28 @@ __global__ __launch_bounds__(512) void route_accumulate_kernel(RouteDev r, int n
         for (uint32_t i = threadIdx.x; i < cnt * F; i += blockDim.x)
             if (sums[i] != 0) unsafeAtomicAdd(out + i, from_fixed(sums[i], inv_scale));
     } else {
-        // All loads of a thread's vectors first, then the adds and stores: one memory round trip.
+        // All loads of a thread's vectors first, then the adds and stores: one memory round trip.  The
+        // gradient is read and written with the non-temporal policy: Adam reads it next, once, and
+        // through the caches it would evict the table that the next inference gathers from (1080p
+        // frame 0.894 -> 0.885 ms).
+        typedef float f4v __attribute__((ext_vector_type(4)));
         const uint32_t nv = vec ? cnt * F / 4 : 0;
         constexpr int V = 8;
         for (uint32_t v0 = threadIdx.x; v0 < nv; v0 += V * blockDim.x) {
-            float4 o[V];
+            f4v o[V];
 #pragma unroll
             for (int u = 0; u < V; ++u) {
                 const uint32_t v = v0 + u * blockDim.x;
-                if (v < nv) o[u] = reinterpret_cast<const float4*>(out)[v];
+                if (v < nv) o[u] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(out) + v);
             }
 #pragma unroll
             for (int u = 0; u < V; ++u) {
                 const uint32_t v = v0 + u * blockDim.x;
                 if (v < nv) {
                     const long long* sv = sums + 4 * v;
-                    reinterpret_cast<float4*>(out)[v] =
-                        make_float4(o[u].x + from_fixed(sv[0], inv_scale), o[u].y + from_fixed(sv[1], inv_scale),
-                                    o[u].z + from_fixed(sv[2], inv_scale), o[u].w + from_fixed(sv[3], inv_scale));
+                    const f4v r = {o[u].x + from_fixed(sv[0], inv_scale), o[u].y + from_fixed(sv[1], inv_scale),
+                                   o[u].z + from_fixed(sv[2], inv_scale), o[u].w + from_fixed(sv[3], inv_scale)};
+                    __builtin_nontemporal_store(r, reinterpret_cast<f4v*>(out) + v);
                 }
             }
         }
